@@ -281,3 +281,21 @@ def test_moments_and_diagnostics_consistent(orc):
     assert d["nonfinite_cells"] == 0
     lat.f[3, 10] = np.nan
     assert lat.diagnostics()["nonfinite_cells"] >= 1
+
+
+def test_trt_rates_and_viscosity(orc):
+    """TRT: the symmetric rate 1/tau sets the viscosity nu = (tau - 1/2)/3
+    (nomenclature table), the antisymmetric one follows from the magic
+    parameter Lambda = (tau+ - 1/2)(tau- - 1/2) = 1/4."""
+    for tau, tau_minus in ((0.6, 3.0), (0.51, 25.5), (0.548, 0.5 + 0.25 / 0.048)):
+        wp, wm = orc.relaxation_rates(tau, 0.25)
+        assert wp == pytest.approx(1.0 / tau) and 1.0 / wm == pytest.approx(tau_minus)
+    n, tau, u0, steps = 32, 0.6, 0.02, 300
+    nu = (tau - 0.5) / 3.0
+    k = 2 * math.pi / n
+    rho, u = wl.taylor_green_fields(n, n, 4, u0)
+    lat = orc.Lattice(n, n, 4, q=19, tau=tau, collision="trt").init(rho, u)
+    e0 = lat.diagnostics()["kinetic_energy"]
+    lat.step(steps)
+    rate = -math.log(lat.diagnostics()["kinetic_energy"] / e0) / steps
+    assert rate / (4 * nu * k * k) == pytest.approx(1.0, abs=1e-2)
