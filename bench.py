@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the lattice Boltzmann hot path on one MI355X.
+
+Workload (one "step" = one fused stream-collide pass over the lattice):
+lid-driven cavity 512^3, D3Q19 TRT (magic 1/4), tau 0.6, lid velocity 0.1
+along y, walls on all faces; FP32 arithmetic with FP16S storage for `value`,
+and the same run with FP32, FP16C, FP16, P16 and FP64 storage reported next
+to it.  Inputs are synthetic (the cavity starts at rest) and resident in HBM
+before timing.
+
+Prints one JSON line: MLUPs/s (10^6 cell updates per second, all cells of the
+box), the HBM roofline of the dominant kernel (algorithmic bytes per launch /
+measured launch time vs 8 TB/s), the L2 velocity error of each FP32 storage
+format against the FP64 GPU path on a 64^3 cavity after 1000 steps, and the
+FP64 CPU reference timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X datasheet HBM3E bandwidth
+HEADLINE = "fp16s"
+OTHERS = ["fp32", "fp16c", "fp16", "p16_0s", "p16_1s", "p16_2c", "fp64"]
+BYTES = {"fp64": 8, "fp32": 4}
+
+
+def ddf_bytes(storage: str) -> int:
+    return BYTES.get(storage, 2)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2112_08926_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cavity(n, storage, tau=0.6, lid=0.1, q=19, collision="trt"):
+    import paper_2112_08926_amd as lbm
+    import lbm_workloads as wl
+    arith = "fp64" if storage == "fp64" else "fp32"
+    p = lbm.make_params(n, n, n, q=q, collision=collision, storage=storage, arith=arith, tau=tau,
+                        wall_u=(0.0, lid, 0.0))
+    g = lbm.Lattices(p)
+    flags = wl.cavity_flags(n, n, n)
+    g.set_boundaries(0, flags)
+    return g, flags
+
+
+def time_steps(g, steps, warmup):
+    """Average time of one step (= one stream-collide launch) over `steps`
+    launches, measured with events on the stream the kernels run on."""
+    import torch
+    stream = g.stream
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def measure_format(storage, n, steps, warmup):
+    g, flags = cavity(n, storage)
+    try:
+        g.step(2)
+        cfg = g.autotune(3)                      # leaves the state unchanged
+        ms = time_steps(g, steps, warmup)
+        d = g.diagnostics(0)
+    finally:
+        g.close()
+    N = n ** 3
+    n_fluid = int(np.count_nonzero(flags == 0))
+    b = ddf_bytes(storage)
+    alg_bytes = n_fluid * (2 * 19 * b + 1) + (N - n_fluid) * 1
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    return {"storage": storage, "ms_per_step": ms, "mlups": N / (ms * 1e-3) / 1e6,
+            "mlups_fluid": n_fluid / (ms * 1e-3) / 1e6, "alg_bytes_per_launch": alg_bytes,
+            "achieved_GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
+            "kinetic_energy": d["kinetic_energy"], "nonfinite": d["nonfinite_cells"],
+            "launch": {"block": cfg["block"], "cells_per_lane": cfg["cells_per_lane"]}}
+
+
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain device copy (the library's copy
+    probe), counted as bytes read + bytes written."""
+    import torch
+    import paper_2112_08926_amd as lbm
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    lbm.lbm_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lbm.lbm_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def accuracy_vs_fp64(formats, n=64, steps=1000):
+    """Relative L2 of u of each storage format against the FP64 GPU path on the
+    same cavity (the FP64 path matches the CPU reference to 1e-12)."""
+    ref_g, _ = cavity(n, "fp64")
+    ref_g.step(steps)
+    _, u_ref = ref_g.get_rho_u(0)
+    ref_g.close()
+    out = {}
+    for s in formats:
+        g, _ = cavity(n, s)
+        g.step(steps)
+        _, u = g.get_rho_u(0)
+        g.close()
+        out[s] = float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+    return out
+
+
+def traffic_from_profile(storage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"ldc512_{storage}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 CPU reference timed on the host cores: the same cavity at a
+    reduced 96^3, D3Q19 TRT, FP64 arithmetic with FP16S storage emulation,
+    as many steps as fit the time budget (at least 2)."""
+    import oracle
+    import lbm_workloads as wl
+    n = 96
+    flags = wl.cavity_flags(n, n, n)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    lat = oracle.Lattice(n, n, n, q=19, tau=0.6, collision="trt", storage=HEADLINE,
+                         wall_u=(0.0, 0.1, 0.0), flags=flags, nthreads=threads).init()
+    t0 = time.perf_counter()
+    lat.step(1)
+    one = time.perf_counter() - t0
+    steps = max(2, int(budget_s / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    lat.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPs/s", "cores": threads, "kind": "oracle",
+            "sample": f"cavity {n}^3 D3Q19 TRT FP64 arithmetic, FP16S storage emulated, {steps} steps, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=512, help="cavity edge length")
+    ap.add_argument("--formats", default="all", help="'all', 'headline' or a comma list")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    import paper_2112_08926_amd  # noqa: F401  (fails loudly without liblbm.so)
+
+    formats = [HEADLINE] + (OTHERS if args.formats == "all" else
+                            ([] if args.formats == "headline" else
+                             [f for f in args.formats.split(",") if f != HEADLINE]))
+    results = {}
+    for s in formats:
+        print(f"[bench] {s} {args.n}^3 ...", file=sys.stderr, flush=True)
+        results[s] = measure_format(s, args.n, args.steps, args.warmup)
+        print(f"[bench] {s}: {results[s]['mlups']:.0f} MLUPs/s, "
+              f"{results[s]['achieved_GBps']:.0f} GB/s, launch {results[s]['launch']}",
+              file=sys.stderr, flush=True)
+    head = results[HEADLINE]
+    print("[bench] copy probe", file=sys.stderr, flush=True)
+    copy_gbs = copy_bandwidth()
+    acc = None
+    if not args.no_accuracy:
+        print("[bench] accuracy vs FP64 (64^3, 1000 steps)", file=sys.stderr, flush=True)
+        acc = accuracy_vs_fp64([s for s in formats if s != "fp64"])
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] CPU reference timing", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+    traffic = traffic_from_profile(HEADLINE)
+    line = {
+        "metric": "MLUPs/s and % of HBM roofline, D3Q19 FP32/16-bit vs FP32/FP32, L2 err vs FP64",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"lid-driven cavity {args.n}^3, D3Q19 TRT (Lambda 1/4), tau 0.6, lid 0.1, "
+                               f"FP32 arithmetic / FP16S storage",
+                   "cells": args.n ** 3, "storage": HEADLINE, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBps"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(head["frac_of_8TBps"], 4),
+                     "traffic": traffic, "copy_probe_GBps": round(copy_gbs, 1),
+                     "frac_of_copy": round(head["achieved_GBps"] / copy_gbs, 4)},
+        "cpu_baseline": cpu,
+        "formats": {s: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                    for s, r in results.items()},
+        "fp16s_vs_fp32_speedup": (round(head["mlups"] / results["fp32"]["mlups"], 3)
+                                  if "fp32" in results else None),
+        "l2_vs_fp64": acc,
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

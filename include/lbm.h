@@ -1,0 +1,212 @@
+/*
+ * lbm.h -- C interface of liblbm.so, an MI355X (gfx950) implementation of the
+ * lattice Boltzmann hot path of Lehmann, Krause, Amati, Sega, Harting, Gekle,
+ * "On the accuracy and performance of the lattice Boltzmann method with
+ * 64-bit, 32-bit and novel 16-bit number formats" (arXiv 2112.08926).
+ *
+ * What the library computes (paper references by section/equation/table):
+ *   - the fused pull stream-collide step of the appendix "LBM equations in a
+ *     nutshell" (streaming, fields, equilibrium, collision) with DDF shifting
+ *     (Sec. 2.2: DDFs stored as f_i - w_i, shifted equilibrium in its 3-FMA
+ *     order, density summed with the 1 added last, velocity summed with
+ *     alternating signs), the velocity clamp and mid-grid bounce-back of the
+ *     paper's D3Q19 SRT kernel listing;
+ *   - velocity sets D3Q19 and D3Q27, collision SRT (BGK) or TRT, Guo body
+ *     force, stationary and moving bounce-back walls, cells held at a fixed
+ *     equilibrium;
+ *   - FP32 arithmetic with DDFs stored as FP32, IEEE FP16, FP16S, FP16C,
+ *     P16_0S, P16_1S or P16_2C (Sec. 3, Table 2), and an FP64 arithmetic path
+ *     with FP64 or FP32 storage;
+ *   - FP64 reductions of mass, momentum, kinetic energy (Sec. 4.2), the L2
+ *     velocity error of Sec. 4.1 and the momentum-exchange force on walls;
+ *   - ensembles of independent lattices of different sizes advanced together.
+ *
+ * Conventions for every function:
+ *   - Status codes are returned, never thrown; lbm_last_error() gives a
+ *     thread-local message for the last failure in the calling thread.
+ *   - Host arrays passed in are borrowed for the duration of the call only.
+ *   - The library owns all device memory it allocates (through the optional
+ *     allocator hooks of lbm_create, else hipMalloc) and frees it in
+ *     lbm_destroy.
+ *   - All device work of a handle is enqueued on the stream given to
+ *     lbm_create.  Only functions that return host data synchronise it.
+ *   - A handle may be used by one thread at a time.
+ *   - Cell index n = x + (y + z*ny)*nx; per-cell vector fields are stored
+ *     component-major: u[0*N + n] = u_x, u[1*N + n] = u_y, u[2*N + n] = u_z.
+ *   - All faces are periodic; walls and inflow/outflow are made with cell
+ *     flags.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_handle lbm_handle;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,        /* invalid argument (message says which) */
+    LBM_ENOMEM = -2,        /* device or host allocation failed */
+    LBM_EDEVICE = -3,       /* a HIP call failed */
+    LBM_EUNSUPPORTED = -4,  /* valid but not built combination */
+    LBM_ENONFINITE = -5     /* diagnostics found non-finite fields */
+} lbm_status;
+
+typedef enum { LBM_D3Q19 = 19, LBM_D3Q27 = 27 } lbm_velset;
+typedef enum { LBM_SRT = 0, LBM_TRT = 1 } lbm_collision;
+
+/* DDF storage formats (Sec. 3, Table 2).  Codes of the 16-bit formats:
+ * FP16 IEEE binary16 (round to nearest even); FP16S binary16 of x*2^15;
+ * FP16C 1|4|11 bits, bias 15, no Inf/NaN; P16_0S and P16_1S posits with 0/1
+ * exponent bits in sign-magnitude form holding x*2^7; P16_2C the asymmetric
+ * posit with 2 exponent bits.  FP16C and the posits round to the nearest
+ * value with ties away from zero and saturate at their largest value. */
+typedef enum {
+    LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2, LBM_FP16S = 3, LBM_FP16C = 4,
+    LBM_P16_0S = 5, LBM_P16_1S = 6, LBM_P16_2C = 7
+} lbm_storage;
+
+/* Arithmetic precision.  LBM_ARITH_FP64 requires FP64 or FP32 storage. */
+typedef enum { LBM_ARITH_FP32 = 0, LBM_ARITH_FP64 = 1 } lbm_arith;
+
+/* Cell flags (one byte per cell). */
+#define LBM_FLAG_SOLID  1u   /* bounce-back wall cell; never updated */
+#define LBM_FLAG_EQ     2u   /* held at the equilibrium of eq_rho, eq_u */
+#define LBM_FLAG_MOVING 4u   /* with SOLID: wall moving with wall_u */
+
+typedef struct {
+    int32_t nx, ny, nz;      /* cells per axis in [1, 65535]; N = nx*ny*nz with
+                                N < 2^31 and N * bytes per DDF < 2^32 */
+    int32_t q;               /* lbm_velset */
+    int32_t collision;       /* lbm_collision */
+    int32_t storage;         /* lbm_storage */
+    int32_t arith;           /* lbm_arith */
+    int32_t reserved;        /* must be 0 */
+    double tau;              /* relaxation time, > 0.5 (nu = (tau - 1/2)/3) */
+    double trt_magic;        /* TRT Lambda = (tau - 1/2)(tau_minus - 1/2); 0.25 */
+    double force[3];         /* Guo body force per volume (lattice units) */
+    double wall_u[3];        /* velocity of MOVING wall cells (wall density 1) */
+    double eq_rho;           /* density of EQ cells */
+    double eq_u[3];          /* velocity of EQ cells */
+} lbm_params;
+
+/* FP64 diagnostics of one lattice, summed over fluid cells (neither SOLID
+ * nor EQ) in a fixed order, so repeated calls give identical results. */
+typedef struct {
+    double mass;             /* sum of rho */
+    double momentum[3];      /* sum of rho u */
+    double kinetic_energy;   /* sum of rho |u|^2 / 2 */
+    double u_max;            /* max |u| */
+    double l2_error;         /* sqrt(sum |u - u_ref|^2 / sum |u_ref|^2); -1 without u_ref */
+    double force_on_solid[3];/* momentum exchange into SOLID cells, this time step */
+    int64_t nonfinite_cells; /* fluid cells with non-finite rho or u */
+    int64_t step;            /* time steps taken since the last initialisation */
+} lbm_diag;
+
+/* How lbm_step launches the stream-collide kernel. */
+typedef enum { LBM_LAUNCH_PER_LATTICE = 0, LBM_LAUNCH_BATCHED = 1 } lbm_launch_mode;
+typedef struct {
+    int32_t mode;            /* lbm_launch_mode */
+    int32_t block;           /* threads per workgroup: 64, 128, 256, 512 */
+    int32_t cells_per_lane;  /* consecutive x cells per thread: 1, 2 (not FP64
+                                storage) or 4 (16-bit storage); every nx must
+                                be a multiple of it */
+    int32_t persistent;      /* batched only: workgroups per CU of a persistent
+                                grid walking the tile table; 0 = one workgroup
+                                per tile */
+    int32_t graph_steps;     /* > 0 (even): lbm_step replays a HIP graph of
+                                this many steps; 0 = direct launches */
+} lbm_launch;
+
+typedef struct {
+    int64_t cells;           /* total cells of all lattices */
+    int64_t device_bytes;    /* device memory held by the handle */
+    int32_t n_lattices;
+    int32_t bytes_per_ddf;   /* 8, 4 or 2 */
+    int64_t step;
+} lbm_info;
+
+typedef void* (*lbm_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*lbm_free_fn)(void* ptr, void* ctx);
+
+/* Create n_lattices >= 1 lattices described by params[0..n_lattices-1].
+ * All must share q, collision, storage and arith (else LBM_EUNSUPPORTED).
+ * stream: a hipStream_t, or NULL for the null stream.  alloc/free_: optional
+ * device allocator (both or neither); alloc_ctx is passed back to them.
+ * Every cell starts as fluid at rest (rho = 1, u = 0).
+ * Errors: LBM_EINVAL for tau <= 0.5, sizes out of range, reserved != 0 or
+ * unknown enums; LBM_ENOMEM; LBM_EDEVICE. */
+lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, void* stream,
+                      lbm_alloc_fn alloc, lbm_free_fn free_, void* alloc_ctx,
+                      lbm_handle** out);
+
+/* Set the cell flags of one lattice from host uint8[N] (bits LBM_FLAG_*;
+ * MOVING without SOLID, and EQ with SOLID, are LBM_EINVAL), then
+ * re-initialise that lattice to rest with EQ cells at their equilibrium.
+ * Wall cells hold zero DDFs. */
+lbm_status lbm_set_boundaries(lbm_handle* h, int32_t lattice, const uint8_t* flags);
+
+/* Initialise one lattice's DDFs to the equilibrium of host fields rho[N] and
+ * u[3*N] (either may be NULL: rho = 1, u = 0), stored in the lattice's
+ * format (the paper's initialize kernel).  EQ cells take eq_rho/eq_u, SOLID
+ * cells zero.  Resets the step counter of the handle. */
+lbm_status lbm_set_rho_u(lbm_handle* h, int32_t lattice, const double* rho, const double* u);
+
+/* Advance every lattice by n_steps >= 0 time steps (asynchronous). */
+lbm_status lbm_step(lbm_handle* h, int64_t n_steps);
+
+/* Density and velocity of the current state (what the next step sees after
+ * streaming; velocity includes half the body force, not clamped).  SOLID
+ * cells report rho = 1 and the wall velocity, EQ cells their own moments.
+ * rho: host double[N] or NULL; u: host double[3*N] or NULL.  Synchronises. */
+lbm_status lbm_get_rho_u(lbm_handle* h, int32_t lattice, double* rho, double* u);
+
+/* Raw DDF codes of the current state: host buffer of q*N elements of the
+ * storage type (double, float or uint16), direction-major [i*N + n].
+ * set: copies in (any values; used for checkpoints and exact comparisons);
+ * get: copies out and synchronises. */
+lbm_status lbm_set_ddf(lbm_handle* h, int32_t lattice, const void* host);
+lbm_status lbm_get_ddf(lbm_handle* h, int32_t lattice, void* host);
+
+/* FP64 diagnostics of one lattice.  u_ref: NULL or host double[3*N] for the
+ * L2 error.  Fills *out; returns LBM_ENONFINITE (after filling) if
+ * out->nonfinite_cells > 0.  Synchronises. */
+lbm_status lbm_diagnostics(lbm_handle* h, int32_t lattice, const double* u_ref, lbm_diag* out);
+
+/* Launch configuration (see lbm_launch); invalid values are LBM_EINVAL. */
+lbm_status lbm_set_launch(lbm_handle* h, const lbm_launch* cfg);
+lbm_status lbm_get_launch(lbm_handle* h, lbm_launch* cfg);
+
+/* Time every launch configuration on the handle's own lattices (trial_steps
+ * kernel launches each, reading the current state and writing the other
+ * buffer, so the state is left unchanged), keep the fastest and return it.
+ * The graph setting of the current configuration is kept. */
+lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launch* best);
+
+lbm_status lbm_info_get(lbm_handle* h, lbm_info* out);
+lbm_status lbm_synchronize(lbm_handle* h);
+void lbm_destroy(lbm_handle* h);
+const char* lbm_last_error(void);
+
+/* Storage codecs on device arrays (Sec. 3): encode n floats into n codes of
+ * a 16-bit format, or decode n codes into floats.  d_in/d_out: device
+ * pointers; stream: hipStream_t or NULL.  Asynchronous.  LBM_EINVAL for a
+ * non-16-bit format or n < 0. */
+lbm_status lbm_encode(int32_t storage, const float* d_in, uint16_t* d_out, int64_t n, void* stream);
+lbm_status lbm_decode(int32_t storage, const uint16_t* d_in, float* d_out, int64_t n, void* stream);
+
+/* Plain device copy of `bytes` bytes (multiple of 16, 16-byte aligned
+ * pointers): the reference kernel for calibrating memory-traffic counters
+ * and achievable HBM bandwidth.  Asynchronous. */
+lbm_status lbm_copy_probe(const void* d_src, void* d_dst, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,161 @@
+// lbm_codecs.h -- conversion between FP32 (or FP64) arithmetic values and the
+// DDF storage formats of Sec. 3 / Table 2 of the paper, for gfx950.
+//
+// Decoders are branch-free bit manipulation (one leading-zero count for the
+// posits).  FP16 and FP16S use the hardware f32<->f16 conversions (round to
+// nearest even).  FP16C and the posits encode through a 256-entry table
+// indexed by the FP32 exponent field: inside one FP32 binade the codes of
+// these formats are either evenly spaced (code = first code + rounded
+// mantissa, the carry running into the next binade) or absent (one threshold
+// between the two neighbouring codes), so
+//     code = base[E] + min((mantissa + bias[E]) >> shift[E], cap[E])
+// rounds every float to the nearest code with ties away from zero, and
+// saturates above the largest code.  The table is built on the host from
+// the decoders below (build_encoder_table in the runtime).
+//
+// Every function here is __host__ __device__ so that the host can build the
+// tables from exactly the device decoders.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+__host__ __device__ __forceinline__ uint32_t f2u(float x) { return __builtin_bit_cast(uint32_t, x); }
+__host__ __device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit_cast(float, u); }
+
+// ---------------------------------------------------------------- FP16C
+// 1 sign | 4 exponent (bias 15) | 11 mantissa, no Inf/NaN.  Placing the 15
+// magnitude bits at FP32 bits 26..12 gives 2^(e-127)(1 + m/2^11), or the FP32
+// denormal m 2^-137 for e = 0; one multiply by 2^112 rebiases both exactly.
+__host__ __device__ __forceinline__ float fp16c_decode(uint32_t c) {
+    const uint32_t bits = ((c & 0x8000u) << 16) | ((c & 0x7FFFu) << 12);
+    return u2f(bits) * 0x1p112f;
+}
+
+// ---------------------------------------------------------------- posits
+// Sign-magnitude posits (Sec. 3.2.3): the 15 magnitude bits are placed at the
+// top of a 32-bit word; the regime is the run of equal leading bits.
+// P16_0S / P16_1S additionally carry the range shift x*2^7, undone here by
+// the exponent bias 127 - 7.
+template <int ES>
+__host__ __device__ __forceinline__ float posit_s_decode(uint32_t c) {
+    const uint32_t mag = c & 0x7FFFu;
+    const uint32_t t = mag << 17;
+    const uint32_t ones = t >> 31;                       // regime of ones (r >= 0)
+    const uint32_t u = ones ? ~t : t;                    // turn the run into zeros
+    const int k = __builtin_clz(u | 1u);                 // run length (mag != 0)
+    const int r = ones ? k - 1 : -k;
+    const uint32_t rest = (t << k) << 1;                 // bits after the terminator
+    uint32_t bits;
+    if (ES == 0)
+        bits = (uint32_t)((r + 120) << 23) + (rest >> 9);
+    else
+        bits = (uint32_t)((2 * r + 120) << 23) + (rest >> 8);   // exponent bit lands on bit 23
+    bits = mag ? bits : 0u;
+    return u2f(bits | ((c & 0x8000u) << 16));
+}
+
+// Asymmetric P16_2C: r leading zeros close with a one (no regime sign), then
+// 2 exponent bits and 12 - r mantissa bits; value 2^(-3-4r+e)(1 + m/2^(12-r)).
+__host__ __device__ __forceinline__ float p162c_decode(uint32_t c) {
+    const uint32_t mag = c & 0x7FFFu;
+    const uint32_t t = mag << 17;
+    const int r = __builtin_clz(t | 1u);
+    const uint32_t rest = (t << r) << 1;                 // exponent bits at 31..30
+    uint32_t bits = (uint32_t)((124 - 4 * r) << 23) + (rest >> 7);
+    bits = mag ? bits : 0u;
+    return u2f(bits | ((c & 0x8000u) << 16));
+}
+
+// ---------------------------------------------------------------- IEEE FP16
+__host__ __device__ __forceinline__ float half_decode(uint32_t c) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)c);
+}
+__host__ __device__ __forceinline__ uint16_t half_encode(float x) {
+    return __builtin_bit_cast(uint16_t, (_Float16)x);
+}
+
+// Software encoder through the per-binade table.
+__host__ __device__ __forceinline__ uint16_t table_encode(float x, const EncEntry* tab) {
+    const uint32_t b = f2u(x);
+    const uint32_t a = b & 0x7FFFFFFFu;
+    const EncEntry e = tab[a >> 23];
+    uint32_t j = ((a & 0x7FFFFFu) + e.bias) >> e.shift;
+    j = j < e.cap ? j : e.cap;
+    return (uint16_t)(((b >> 16) & 0x8000u) | (e.base + j));
+}
+
+// Decoded value of a 16-bit code of a format (host table builder and tests).
+__host__ __device__ __forceinline__ float decode16(int fmt, uint32_t c) {
+    switch (fmt) {
+    case S_FP16:   return half_decode(c);
+    case S_FP16S:  return half_decode(c) * 0x1p-15f;
+    case S_FP16C:  return fp16c_decode(c);
+    case S_P16_0S: return posit_s_decode<0>(c);
+    case S_P16_1S: return posit_s_decode<1>(c);
+    case S_P16_2C: return p162c_decode(c);
+    default:       return 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------- storage traits
+// Codec<F>::T is the stored type; load() returns the arithmetic value, store()
+// takes it.  `tab` is the encoder table in LDS (used by FP16C and posits).
+template <int F> struct Codec;
+
+template <> struct Codec<S_FP64> {
+    using T = double;
+    static constexpr bool kTable = false;
+    template <class A> __device__ __forceinline__ static A load(T v) { return (A)v; }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return (T)v; }
+};
+template <> struct Codec<S_FP32> {
+    using T = float;
+    static constexpr bool kTable = false;
+    template <class A> __device__ __forceinline__ static A load(T v) { return (A)v; }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return (T)v; }
+};
+template <> struct Codec<S_FP16> {
+    using T = uint16_t;
+    static constexpr bool kTable = false;
+    template <class A> __device__ __forceinline__ static A load(T v) { return half_decode(v); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return half_encode(v); }
+};
+template <> struct Codec<S_FP16S> {
+    using T = uint16_t;
+    static constexpr bool kTable = false;
+    template <class A> __device__ __forceinline__ static A load(T v) { return half_decode(v) * 0x1p-15f; }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) {
+        return half_encode(v * 32768.0f);
+    }
+};
+template <> struct Codec<S_FP16C> {
+    using T = uint16_t;
+    static constexpr bool kTable = true;
+    template <class A> __device__ __forceinline__ static A load(T v) { return fp16c_decode(v); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
+};
+template <> struct Codec<S_P16_0S> {
+    using T = uint16_t;
+    static constexpr bool kTable = true;
+    template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode<0>(v); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
+};
+template <> struct Codec<S_P16_1S> {
+    using T = uint16_t;
+    static constexpr bool kTable = true;
+    template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode<1>(v); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
+};
+template <> struct Codec<S_P16_2C> {
+    using T = uint16_t;
+    static constexpr bool kTable = true;
+    template <class A> __device__ __forceinline__ static A load(T v) { return p162c_decode(v); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
+};
+
+}  // namespace lbm

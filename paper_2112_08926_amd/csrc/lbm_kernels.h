@@ -1,0 +1,780 @@
+// lbm_kernels.h -- HIP kernels of the fused pull stream-collide step and its
+// companions (initialisation, moments, FP64 diagnostics) for gfx950.
+//
+// Method (paper: appendix "LBM equations in a nutshell" with DDF shifting,
+// Sec. 2.2, and the D3Q19 SRT kernel listing):
+//   pull:     f_i(x) <- f_i^A(x - c_i); a wall source gives f_opp(i)^A(x)
+//             (mid-grid bounce-back), plus 6 w_i c_i.u_w off a moving wall;
+//   fields:   rho = f_0 + f_1 + ... + 1 (the 1 last), rho u = alternating
+//             pair sums (+ F/2 with the Guo force), u clamped to +-c;
+//   feq:      w_i rho (1/2 (B^2 + C) + B) + w_i (rho - 1), B = 3 c_i.u,
+//             C = -3 u.u -- three FMAs per direction;
+//   collide:  SRT f' = (1 - w) f + w feq (+ (1 - w/2) S_i), or TRT on the
+//             symmetric/antisymmetric parts of each opposite pair;
+//   store:    f'_i -> B at x, encoded in the storage format.
+//
+// Work decomposition (one lattice, or one tile of an ensemble): a workgroup
+// owns `block` consecutive cells of one x-row (y, z).  The nine source rows
+// (y +- 1, z +- 1) and their periodic wrap are workgroup-uniform, so every
+// direction's source address is a scalar base (plane + source row) plus a
+// per-lane x offset from {x-1, x, x+1}: no integer division per cell, and
+// each direction is one contiguous, coalesced segment of a source row.  A
+// row's x-shifted loads stay inside that row (periodic wrap), so a row's
+// cache lines are fetched by one workgroup only.  Neighbour flags are read
+// only by wavefronts that contain a cell next to a wall (F_NEAR).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_codecs.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------ velocity sets
+// D3Q19: 0 rest, then opposite pairs in the order of the paper's listing
+// (+00 -00, 0+0 0-0, 00+ 00-, ++0 --0, +0+ -0-, 0++ 0--, +-0 -+0, +0- -0+,
+// 0+- 0-+); weights 1/3, 1/18, 1/36.  D3Q27 appends the corner pairs
+// (+++ ---, ++- --+, +-+ -+-, -++ +--); weights 8/27, 2/27, 1/54, 1/216.
+template <int Q> struct VelSet;
+
+struct VelSetTables {
+    static constexpr int c[27][3] = {
+        { 0, 0, 0},
+        { 1, 0, 0}, {-1, 0, 0}, { 0, 1, 0}, { 0,-1, 0}, { 0, 0, 1}, { 0, 0,-1},
+        { 1, 1, 0}, {-1,-1, 0}, { 1, 0, 1}, {-1, 0,-1}, { 0, 1, 1}, { 0,-1,-1},
+        { 1,-1, 0}, {-1, 1, 0}, { 1, 0,-1}, {-1, 0, 1}, { 0, 1,-1}, { 0,-1, 1},
+        { 1, 1, 1}, {-1,-1,-1}, { 1, 1,-1}, {-1,-1, 1}, { 1,-1, 1}, {-1, 1,-1},
+        {-1, 1, 1}, { 1,-1,-1}};
+};
+
+template <> struct VelSet<19> : VelSetTables {
+    static constexpr int Q = 19;
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+};
+template <> struct VelSet<27> : VelSetTables {
+    static constexpr int Q = 27;
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 8.0 / 27.0 : (i < 7 ? 2.0 / 27.0 : (i < 19 ? 1.0 / 54.0 : 1.0 / 216.0));
+    }
+};
+
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+template <class A> __device__ __forceinline__ A clamp_c(A v) {
+    const A cs = (A)0.57735026918962576451;   // lattice speed of sound 1/sqrt(3)
+    return v < -cs ? -cs : (v > cs ? cs : v);
+}
+
+// c . v for a lattice direction with components in {-1, 0, 1}, written with
+// additions only (a multiply by a zero component is not foldable in IEEE
+// arithmetic); the components are compile-time constants after unrolling.
+template <class A>
+__device__ __forceinline__ A cdot(int cx, int cy, int cz, A x, A y, A z) {
+    A s = cx > 0 ? x : (cx < 0 ? -x : (A)0);
+    bool any = cx != 0;
+    if (cy != 0) { s = any ? (cy > 0 ? s + y : s - y) : (cy > 0 ? y : -y); any = true; }
+    if (cz != 0) { s = any ? (cz > 0 ? s + z : s - z) : (cz > 0 ? z : -z); any = true; }
+    return s;
+}
+template <int Q, class A>
+__device__ __forceinline__ A cdot_i(int i, A x, A y, A z) {
+    return cdot<A>(VelSet<Q>::c[i][0], VelSet<Q>::c[i][1], VelSet<Q>::c[i][2], x, y, z);
+}
+
+// ------------------------------------------------------------ geometry of a row
+struct RowCtx {
+    uint32_t rows[9];   // cell index of x = 0 of row (y+dy, z+dz), index (dy+1) + 3 (dz+1)
+};
+
+__device__ __forceinline__ uint32_t wrap_add(uint32_t a, int d, uint32_t n) {
+    return d < 0 ? (a == 0 ? n - 1 : a - 1) : (d > 0 ? (a + 1 == n ? 0 : a + 1) : a);
+}
+
+__device__ __forceinline__ void make_rows(const LatDev& L, uint32_t y, uint32_t z, RowCtx& rc) {
+#pragma unroll
+    for (int dz = -1; dz <= 1; dz++)
+#pragma unroll
+        for (int dy = -1; dy <= 1; dy++) {
+            const uint32_t yy = wrap_add(y, dy, L.ny), zz = wrap_add(z, dz, L.nz);
+            rc.rows[(dy + 1) + 3 * (dz + 1)] = (yy + zz * L.ny) * L.nx;
+        }
+}
+
+// Source row and x of direction i for a cell at (x, row (y, z)): x - c_i.
+template <int Q>
+__device__ __forceinline__ uint32_t src_row(const RowCtx& rc, int i) {
+    return rc.rows[(1 - VelSet<Q>::c[i][1]) + 3 * (1 - VelSet<Q>::c[i][2])];
+}
+template <int Q>
+__device__ __forceinline__ uint32_t src_x(int i, uint32_t x, uint32_t xm, uint32_t xp) {
+    return VelSet<Q>::c[i][0] > 0 ? xm : (VelSet<Q>::c[i][0] < 0 ? xp : x);
+}
+
+// ------------------------------------------------------------ pull with bounce-back
+template <int Q, int F, class A>
+__device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
+                                     const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp,
+                                     uint32_t n, bool near, A (&f)[Q]) {
+    using T = typename Codec<F>::T;
+    const size_t plane = L.plane;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
+        f[i] = Codec<F>::template load<A>(p[src_x<Q>(i, x, xm, xp)]);
+    }
+    if (__any(near)) {
+        // A wall source hands back what this cell sent towards it last step.
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
+            if (near && (fs & F_SOLID)) {
+                A v = Codec<F>::template load<A>(src[(size_t)opp(i) * plane + n]);
+                if (fs & F_MOVING) {
+                    const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                     VelSet<Q>::c[i][2] * L.wall_u[2]);
+                    v += (A)(6.0 * VelSet<Q>::w(i)) * cu;
+                }
+                f[i] = v;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ fields
+template <int Q, class A>
+__device__ __forceinline__ void fields(const A (&f)[Q], A& rho, A (&j)[3]) {
+    A r = f[0];
+#pragma unroll
+    for (int i = 1; i < Q; i++) r += f[i];
+    rho = r + (A)1;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        A s = (A)0;
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            const int c = VelSet<Q>::c[i][a];
+            if (c > 0) { s += f[i]; s -= f[i + 1]; }
+            else if (c < 0) { s += f[i + 1]; s -= f[i]; }
+        }
+        j[a] = s;
+    }
+}
+
+// ------------------------------------------------------------ collision
+// Computes the post-collision DDFs fo[] of one cell from the pulled f[].
+// EXACT_DIV: u = j / rho as the paper's listing divides (FP32/FP64 storage,
+// where the division's rounding is visible); otherwise j * (1/rho), whose
+// extra rounding (1e-7 relative) is far below a 16-bit storage step.
+template <int Q, int COLL, class A, bool EXACT_DIV>
+__device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo)[Q]) {
+    A rho, j[3];
+    fields<Q, A>(f, rho, j);
+    const bool forced = L.forced != 0;
+    const A Fx = (A)L.force[0], Fy = (A)L.force[1], Fz = (A)L.force[2];
+    if (forced) {
+        j[0] += (A)0.5 * Fx;
+        j[1] += (A)0.5 * Fy;
+        j[2] += (A)0.5 * Fz;
+    }
+    A ux, uy, uz;
+    if constexpr (EXACT_DIV) {
+        ux = clamp_c(j[0] / rho);
+        uy = clamp_c(j[1] / rho);
+        uz = clamp_c(j[2] / rho);
+    } else {
+        const A inv = (A)1 / rho;
+        ux = clamp_c(j[0] * inv);
+        uy = clamp_c(j[1] * inv);
+        uz = clamp_c(j[2] * inv);
+    }
+    const A C = (A)(-3) * (ux * ux + uy * uy + uz * uz);
+    const A rhom1 = rho - (A)1;
+    const A u3x = (A)3 * ux, u3y = (A)3 * uy, u3z = (A)3 * uz;
+    const A w = (A)L.omega, wm = (A)L.omega_m;
+    const A uF = ux * Fx + uy * Fy + uz * Fz;
+
+    A feq[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const A wi = (A)VelSet<Q>::w(i);
+        const A B = cdot_i<Q, A>(i, u3x, u3y, u3z);
+        feq[i] = __builtin_fma(wi * rho, __builtin_fma((A)0.5, __builtin_fma(B, B, C), B), wi * rhom1);
+    }
+    if (COLL == 0) {
+        const A omw = (A)1 - w;
+#pragma unroll
+        for (int i = 0; i < Q; i++) fo[i] = __builtin_fma(omw, f[i], w * feq[i]);
+        if (forced) {
+            const A pre = (A)1 - (A)0.5 * w;
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const A wi = (A)VelSet<Q>::w(i);
+                const A cF = cdot_i<Q, A>(i, Fx, Fy, Fz);
+                const A cu = cdot_i<Q, A>(i, ux, uy, uz);
+                const A sym = wi * ((A)9 * cu * cF - (A)3 * uF);
+                const A anti = wi * (A)3 * cF;
+                fo[i] += pre * (sym + anti);
+            }
+        }
+    } else {
+        fo[0] = f[0] - w * (f[0] - feq[0]);
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            const A fp = (A)0.5 * (f[i] + f[i + 1]), fm = (A)0.5 * (f[i] - f[i + 1]);
+            const A ep = (A)0.5 * (feq[i] + feq[i + 1]), em = (A)0.5 * (feq[i] - feq[i + 1]);
+            fo[i] = f[i] - w * (fp - ep) - wm * (fm - em);
+            fo[i + 1] = f[i + 1] - w * (fp - ep) + wm * (fm - em);
+        }
+        if (forced) {
+            const A prep = (A)1 - (A)0.5 * w, prem = (A)1 - (A)0.5 * wm;
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const A wi = (A)VelSet<Q>::w(i);
+                const A cF = cdot_i<Q, A>(i, Fx, Fy, Fz);
+                const A cu = cdot_i<Q, A>(i, ux, uy, uz);
+                const A sym = wi * ((A)9 * cu * cF - (A)3 * uF);
+                const A anti = wi * (A)3 * cF;
+                fo[i] += prep * sym + prem * anti;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ one tile of the step
+template <int Q, int F, class A, int COLL>
+__device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z,
+                                          int parity, const EncEntry* tab) {
+    using T = typename Codec<F>::T;
+    const uint32_t x = x0 + threadIdx.x;
+    if (x >= L.nx) return;
+    RowCtx rc;
+    make_rows(L, y, z, rc);
+    const uint32_t n = rc.rows[4] + x;
+    const uint8_t fl = L.flags[n];
+    if (fl & (F_SOLID | F_EQ)) return;
+    const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
+    const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+    const T* __restrict__ src = (const T*)L.f[parity];
+    T* __restrict__ dst = (T*)L.f[parity ^ 1];
+
+    A f[Q], fo[Q];
+    pull<Q, F, A>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+    collide<Q, COLL, A, (sizeof(T) >= 4)>(L, f, fo);
+    const size_t plane = L.plane;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        T* p = dst + ((size_t)i * plane + rc.rows[4]);
+        p[x] = Codec<F>::template store<A>(fo[i], tab);
+    }
+}
+
+// ------------------------------------------------------------ several cells per lane
+// A lane owns CPL consecutive cells x .. x+CPL-1 of a row (x a multiple of
+// CPL, nx a multiple of CPL), so each direction is one aligned vector load
+// of CPL stored DDFs and each result one aligned vector store.  Directions
+// with c_x = +1 need the elements x-1 .. x+CPL-2: the lane's own vector
+// shifted by one element, with the missing element taken from the previous
+// lane's vector (cross-lane shift); the first lane of a wavefront loads it
+// directly (periodic wrap at x = 0).  c_x = -1 mirrors this with the next
+// lane.  Row vectors are kept as 32-bit words.
+template <class T, int CPL>
+struct RowVec {
+    static constexpr int W = CPL * (int)sizeof(T) / 4;   // 32-bit words
+    uint32_t w[W];
+};
+
+template <class T, int CPL>
+__device__ __forceinline__ RowVec<T, CPL> vload(const T* p) {
+    RowVec<T, CPL> r;
+    constexpr int W = RowVec<T, CPL>::W;
+    if constexpr (W == 1) {
+        r.w[0] = *(const uint32_t*)p;
+    } else if constexpr (W == 2) {
+        const uint2 v = *(const uint2*)p;
+        r.w[0] = v.x; r.w[1] = v.y;
+    } else {
+        static_assert(W % 4 == 0, "row vector width");
+#pragma unroll
+        for (int k = 0; k < W / 4; k++) {
+            const uint4 v = ((const uint4*)p)[k];
+            r.w[4 * k] = v.x; r.w[4 * k + 1] = v.y; r.w[4 * k + 2] = v.z; r.w[4 * k + 3] = v.w;
+        }
+    }
+    return r;
+}
+
+template <class T, int CPL>
+__device__ __forceinline__ void vstore(T* p, const RowVec<T, CPL>& r) {
+    constexpr int W = RowVec<T, CPL>::W;
+    if constexpr (W == 1) {
+        *(uint32_t*)p = r.w[0];
+    } else if constexpr (W == 2) {
+        *(uint2*)p = make_uint2(r.w[0], r.w[1]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < W / 4; k++)
+            ((uint4*)p)[k] = make_uint4(r.w[4 * k], r.w[4 * k + 1], r.w[4 * k + 2], r.w[4 * k + 3]);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T from_bits64(uint64_t b) {
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, b);
+    else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, (uint32_t)b);
+    else return (T)b;
+}
+template <class T>
+__device__ __forceinline__ uint64_t to_bits64(T v) {
+    if constexpr (sizeof(T) == 8) return __builtin_bit_cast(uint64_t, v);
+    else if constexpr (sizeof(T) == 4) return __builtin_bit_cast(uint32_t, v);
+    else return (uint16_t)v;
+}
+
+template <class T, int CPL>
+__device__ __forceinline__ T velem(const RowVec<T, CPL>& r, int k) {
+    if constexpr (sizeof(T) == 2) return (T)(r.w[k >> 1] >> (16 * (k & 1)));
+    else if constexpr (sizeof(T) == 4) return from_bits64<T>(r.w[k]);
+    else return from_bits64<T>((uint64_t)r.w[2 * k] | ((uint64_t)r.w[2 * k + 1] << 32));
+}
+
+template <class T, int CPL>
+__device__ __forceinline__ void vset(RowVec<T, CPL>& r, int k, T v) {
+    const uint64_t b = to_bits64<T>(v);
+    if constexpr (sizeof(T) == 2) {
+        if (k & 1) r.w[k >> 1] = (r.w[k >> 1] & 0xFFFFu) | ((uint32_t)b << 16);
+        else r.w[k >> 1] = (uint32_t)b;    // even element is set first
+    } else if constexpr (sizeof(T) == 4) {
+        r.w[k] = (uint32_t)b;
+    } else {
+        r.w[2 * k] = (uint32_t)b;
+        r.w[2 * k + 1] = (uint32_t)(b >> 32);
+    }
+}
+
+// Elements (prev, in[0], ..., in[CPL-2]): `prev` is the element before the
+// vector, `in` shifted up by one element.
+template <class T, int CPL>
+__device__ __forceinline__ RowVec<T, CPL> shift_up(const RowVec<T, CPL>& in, T prev) {
+    RowVec<T, CPL> o;
+    constexpr int W = RowVec<T, CPL>::W;
+    if constexpr (sizeof(T) == 2) {
+        o.w[0] = __builtin_amdgcn_alignbit(in.w[0], (uint32_t)(uint16_t)prev << 16, 16);
+#pragma unroll
+        for (int j = 1; j < W; j++) o.w[j] = __builtin_amdgcn_alignbit(in.w[j], in.w[j - 1], 16);
+    } else {
+        constexpr int E = (int)sizeof(T) / 4;              // words per element
+        const uint64_t b = to_bits64<T>(prev);
+        o.w[0] = (uint32_t)b;
+        if constexpr (E == 2) o.w[1] = (uint32_t)(b >> 32);
+#pragma unroll
+        for (int j = E; j < W; j++) o.w[j] = in.w[j - E];
+    }
+    return o;
+}
+
+// Elements (in[1], ..., in[CPL-1], next).
+template <class T, int CPL>
+__device__ __forceinline__ RowVec<T, CPL> shift_down(const RowVec<T, CPL>& in, T next) {
+    RowVec<T, CPL> o;
+    constexpr int W = RowVec<T, CPL>::W;
+    if constexpr (sizeof(T) == 2) {
+#pragma unroll
+        for (int j = 0; j < W - 1; j++) o.w[j] = __builtin_amdgcn_alignbit(in.w[j + 1], in.w[j], 16);
+        o.w[W - 1] = __builtin_amdgcn_alignbit((uint32_t)(uint16_t)next, in.w[W - 1], 16);
+    } else {
+        constexpr int E = (int)sizeof(T) / 4;
+#pragma unroll
+        for (int j = 0; j < W - E; j++) o.w[j] = in.w[j + E];
+        const uint64_t b = to_bits64<T>(next);
+        o.w[W - E] = (uint32_t)b;
+        if constexpr (E == 2) o.w[W - 1] = (uint32_t)(b >> 32);
+    }
+    return o;
+}
+
+template <class T>
+__device__ __forceinline__ T shfl_elem_up(T v) {
+    const uint64_t b = to_bits64<T>(v);
+    uint64_t r = (uint32_t)__shfl_up((int)(uint32_t)b, 1u, 64);
+    if constexpr (sizeof(T) == 8) r |= (uint64_t)(uint32_t)__shfl_up((int)(uint32_t)(b >> 32), 1u, 64) << 32;
+    return from_bits64<T>(r);
+}
+template <class T>
+__device__ __forceinline__ T shfl_elem_down(T v) {
+    const uint64_t b = to_bits64<T>(v);
+    uint64_t r = (uint32_t)__shfl_down((int)(uint32_t)b, 1u, 64);
+    if constexpr (sizeof(T) == 8) r |= (uint64_t)(uint32_t)__shfl_down((int)(uint32_t)(b >> 32), 1u, 64) << 32;
+    return from_bits64<T>(r);
+}
+
+template <int CPL>
+__device__ __forceinline__ uint32_t load_flags(const uint8_t* p) {
+    if constexpr (CPL == 1) return *p;
+    else if constexpr (CPL == 2) return *(const uint16_t*)p;
+    else return *(const uint32_t*)p;
+}
+
+template <int Q, int F, class A, int COLL, int CPL>
+__device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z,
+                                            int parity, const EncEntry* tab) {
+    using T = typename Codec<F>::T;
+    using RV = RowVec<T, CPL>;
+    const uint32_t nx = L.nx;
+    const uint32_t x = x0 + threadIdx.x * CPL;
+    if (x >= nx) return;
+    const uint32_t lane = threadIdx.x & 63;
+    RowCtx rc;
+    make_rows(L, y, z, rc);
+    const uint32_t row = rc.rows[4];
+    const uint32_t fl4 = load_flags<CPL>(L.flags + row + x);
+    bool near[CPL], special[CPL];
+    bool any_special = false;
+#pragma unroll
+    for (int k = 0; k < CPL; k++) {
+        const uint32_t fk = (fl4 >> (8 * k)) & 0xFF;
+        near[k] = (fk & F_NEAR) != 0;
+        special[k] = (fk & (F_SOLID | F_EQ)) != 0;
+        any_special |= special[k];
+    }
+    const T* __restrict__ src = (const T*)L.f[parity];
+    T* __restrict__ dst = (T*)L.f[parity ^ 1];
+    const size_t plane = L.plane;
+    const bool first_lane = lane == 0;
+    const bool last_lane = lane == 63 || x + CPL == nx;
+    const uint32_t xm = x == 0 ? nx - 1 : x - 1;
+    const uint32_t xn = x + CPL == nx ? 0 : x + CPL;
+
+    RV raw[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
+        const RV v = vload<T, CPL>(p + x);
+        if (VelSet<Q>::c[i][0] > 0) {
+            T prev = shfl_elem_up<T>(velem<T, CPL>(v, CPL - 1));
+            if (first_lane) prev = p[xm];
+            raw[i] = shift_up<T, CPL>(v, prev);
+        } else if (VelSet<Q>::c[i][0] < 0) {
+            T next = shfl_elem_down<T>(velem<T, CPL>(v, 0));
+            if (last_lane) next = p[xn];
+            raw[i] = shift_down<T, CPL>(v, next);
+        } else {
+            raw[i] = v;
+        }
+    }
+
+    RV out[Q];
+#pragma unroll
+    for (int k = 0; k < CPL; k++) {
+        A f[Q], fo[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) f[i] = Codec<F>::template load<A>(velem<T, CPL>(raw[i], k));
+        if (__any(near[k])) {
+            const uint32_t xk = x + k;
+            const uint32_t xkm = xk == 0 ? nx - 1 : xk - 1;
+            const uint32_t xkp = xk + 1 == nx ? 0 : xk + 1;
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, xk, xkm, xkp)];
+                if (near[k] && (fs & F_SOLID)) {
+                    A v = Codec<F>::template load<A>(src[(size_t)opp(i) * plane + row + xk]);
+                    if (fs & F_MOVING) {
+                        const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                         VelSet<Q>::c[i][2] * L.wall_u[2]);
+                        v += (A)(6.0 * VelSet<Q>::w(i)) * cu;
+                    }
+                    f[i] = v;
+                }
+            }
+        }
+        collide<Q, COLL, A, (sizeof(T) >= 4)>(L, f, fo);
+#pragma unroll
+        for (int i = 0; i < Q; i++) vset<T, CPL>(out[i], k, Codec<F>::template store<A>(fo[i], tab));
+    }
+    if (__any(any_special)) {
+        // wall and equilibrium cells keep their DDFs: element-wise stores
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            T* p = dst + ((size_t)i * plane + row + x);
+#pragma unroll
+            for (int k = 0; k < CPL; k++)
+                if (!special[k]) p[k] = velem<T, CPL>(out[i], k);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) vstore<T, CPL>(dst + ((size_t)i * plane + row + x), out[i]);
+    }
+}
+
+template <int F>
+__device__ __forceinline__ const EncEntry* stage_table(const EncEntry* g, EncEntry* s) {
+    if constexpr (Codec<F>::kTable) {
+        for (int k = threadIdx.x; k < 256; k += blockDim.x) s[k] = g[k];
+        __syncthreads();
+        return s;
+    } else {
+        return nullptr;
+    }
+}
+
+// One lattice: workgroup b handles segment b % segs of row b / segs.
+template <int Q, int F, class A, int COLL, int CPL>
+__device__ __forceinline__ void run_tile(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z, int parity,
+                                         const EncEntry* tab) {
+    if constexpr (CPL == 1) step_tile<Q, F, A, COLL>(L, x0, y, z, parity, tab);
+    else step_tile_v<Q, F, A, COLL, CPL>(L, x0, y, z, parity, tab);
+}
+
+template <int Q, int F, class A, int COLL, int CPL>
+__global__ void __launch_bounds__(512) k_step_single(LatDev L, int parity, uint32_t segs,
+                                                     const EncEntry* __restrict__ enc) {
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    const EncEntry* tab = stage_table<F>(enc, s_tab);
+    const uint32_t b = blockIdx.x;
+    const uint32_t seg = b % segs, row = b / segs;
+    const uint32_t y = row % L.ny, z = row / L.ny;
+    run_tile<Q, F, A, COLL, CPL>(L, seg * blockDim.x * CPL, y, z, parity, tab);
+}
+
+// Ensemble: workgroups walk the tile table (one tile each, or a persistent
+// grid-stride walk when the grid is smaller than the table).
+template <int Q, int F, class A, int COLL, int CPL>
+__global__ void __launch_bounds__(512) k_step_batched(const LatDev* __restrict__ lats,
+                                                      const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                      int parity, const EncEntry* __restrict__ enc) {
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    const EncEntry* tab = stage_table<F>(enc, s_tab);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        run_tile<Q, F, A, COLL, CPL>(lats[tl.lat], tl.x0, tl.y, tl.z, parity, tab);
+    }
+}
+
+// ------------------------------------------------------------ initialisation
+// DDFs of the (shifted) equilibrium of rho, u (the paper's initialize kernel)
+// written to both buffers; wall cells get zeros, EQ cells eq_rho/eq_u.
+template <int Q, int F, class A>
+__global__ void __launch_bounds__(256) k_init(LatDev L, const double* __restrict__ rho_in,
+                                              const double* __restrict__ u_in,
+                                              const EncEntry* __restrict__ enc) {
+    using T = typename Codec<F>::T;
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    const EncEntry* tab = stage_table<F>(enc, s_tab);
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const uint8_t fl = L.flags[n];
+    A rho = (A)1, ux = (A)0, uy = (A)0, uz = (A)0;
+    if (fl & F_EQ) {
+        rho = (A)L.eq_rho; ux = (A)L.eq_u[0]; uy = (A)L.eq_u[1]; uz = (A)L.eq_u[2];
+    } else {
+        if (rho_in) rho = (A)rho_in[n];
+        if (u_in) { ux = (A)u_in[n]; uy = (A)u_in[N + n]; uz = (A)u_in[2 * N + n]; }
+    }
+    const A C = (A)(-3) * (ux * ux + uy * uy + uz * uz);
+    const A rhom1 = rho - (A)1;
+    T* d0 = (T*)L.f[0];
+    T* d1 = (T*)L.f[1];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const A wi = (A)VelSet<Q>::w(i);
+        const A B = (A)3 * cdot_i<Q, A>(i, ux, uy, uz);
+        A v = __builtin_fma(wi * rho, __builtin_fma((A)0.5, __builtin_fma(B, B, C), B), wi * rhom1);
+        if (fl & F_SOLID) v = (A)0;
+        const T code = Codec<F>::template store<A>(v, tab);
+        d0[(size_t)i * L.plane + n] = code;
+        d1[(size_t)i * L.plane + n] = code;
+    }
+}
+
+// ------------------------------------------------------------ per-cell moments
+// rho, u the next step sees (velocity with F/2, not clamped); walls: rho 1 and
+// wall velocity; EQ cells: moments of their own DDFs.
+template <int Q, int F, class A>
+__device__ __forceinline__ void cell_moments(const LatDev& L, int parity, uint32_t n, uint32_t& fl_out,
+                                             A& rho, A (&u)[3], A (&f)[Q]) {
+    using T = typename Codec<F>::T;
+    const T* __restrict__ src = (const T*)L.f[parity];
+    const uint32_t x = n % L.nx, yz = n / L.nx, y = yz % L.ny, z = yz / L.ny;
+    const uint8_t fl = L.flags[n];
+    fl_out = fl;
+    if (fl & F_SOLID) {
+        rho = (A)1;
+        const bool mv = fl & F_MOVING;
+        for (int a = 0; a < 3; a++) u[a] = mv ? (A)L.wall_u[a] : (A)0;
+        return;
+    }
+    A j[3];
+    if (fl & F_EQ) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) f[i] = Codec<F>::template load<A>(src[(size_t)i * L.plane + n]);
+        fields<Q, A>(f, rho, j);
+    } else {
+        RowCtx rc;
+        make_rows(L, y, z, rc);
+        const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
+        const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+        pull<Q, F, A>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+        fields<Q, A>(f, rho, j);
+        if (L.forced) {
+            for (int a = 0; a < 3; a++) j[a] += (A)0.5 * (A)L.force[a];
+        }
+    }
+    for (int a = 0; a < 3; a++) u[a] = j[a] / rho;
+}
+
+template <int Q, int F, class A>
+__global__ void __launch_bounds__(256) k_moments(LatDev L, int parity, double* __restrict__ rho_out,
+                                                 double* __restrict__ u_out) {
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    uint32_t fl;
+    A rho, u[3], f[Q];
+    cell_moments<Q, F, A>(L, parity, (uint32_t)n, fl, rho, u, f);
+    if (rho_out) rho_out[n] = (double)rho;
+    if (u_out) {
+        u_out[n] = (double)u[0];
+        u_out[N + n] = (double)u[1];
+        u_out[2 * N + n] = (double)u[2];
+    }
+}
+
+// ------------------------------------------------------------ FP64 diagnostics
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide reduction of kDiagFields values (the last one by max) in a fixed
+// order; thread 0 writes them to out.
+__device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], double* out) {
+    __shared__ double s[kDiagFields][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < kDiagFields; k++) {
+        const double v = (k == kDiagFields - 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) s[k][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kDiagFields; k++) {
+            double v = s[k][0];
+            for (int w = 1; w < nw; w++) v = (k == kDiagFields - 1) ? fmax(v, s[k][w]) : v + s[k][w];
+            out[k] = v;
+        }
+    }
+}
+
+// First pass: a fixed grid of kDiagBlocks workgroups, each a fixed strided
+// subset of the cells, so the result does not depend on timing.
+template <int Q, int F, class A>
+__global__ void __launch_bounds__(256) k_diag(LatDev L, int parity, const double* __restrict__ u_ref,
+                                              double* __restrict__ partials) {
+    using T = typename Codec<F>::T;
+    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    double acc[kDiagFields];
+    for (int k = 0; k < kDiagFields; k++) acc[k] = 0.0;
+    const T* __restrict__ src = (const T*)L.f[parity];
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+        uint32_t fl;
+        A rho, u[3], f[Q];
+        cell_moments<Q, F, A>(L, parity, (uint32_t)n, fl, rho, u, f);
+        if (fl & (F_SOLID | F_EQ)) continue;
+        const double r = (double)rho, ux = (double)u[0], uy = (double)u[1], uz = (double)u[2];
+        if (!(isfinite(r) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
+            acc[10] += 1.0;
+            continue;
+        }
+        acc[0] += r;
+        acc[1] += r * ux;
+        acc[2] += r * uy;
+        acc[3] += r * uz;
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        acc[4] += 0.5 * r * u2;
+        acc[11] = fmax(acc[11], sqrt(u2));
+        if (u_ref) {
+            const double rx = u_ref[n], ry = u_ref[N + n], rz = u_ref[2 * N + n];
+            acc[5] += (ux - rx) * (ux - rx) + (uy - ry) * (uy - ry) + (uz - rz) * (uz - rz);
+            acc[6] += rx * rx + ry * ry + rz * rz;
+        }
+        if (fl & F_NEAR) {
+            // momentum exchange: every link to a wall source carries
+            // c_opp (2 (f*_opp + w_opp) + 6 w_i c_i.u_w) into the wall
+            const uint32_t x = n % L.nx, yz = n / L.nx, y = yz % L.ny, z = yz / L.ny;
+            RowCtx rc;
+            make_rows(L, y, z, rc);
+            const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
+            const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
+                if (!(fs & F_SOLID)) continue;
+                const int o = opp(i);
+                const double fo = (double)Codec<F>::template load<A>(src[(size_t)o * L.plane + n]) + VelSet<Q>::w(o);
+                double mv = 0.0;
+                if (fs & F_MOVING)
+                    mv = 6.0 * VelSet<Q>::w(i) * (VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                                  VelSet<Q>::c[i][2] * L.wall_u[2]);
+                acc[7] += VelSet<Q>::c[o][0] * (2.0 * fo + mv);
+                acc[8] += VelSet<Q>::c[o][1] * (2.0 * fo + mv);
+                acc[9] += VelSet<Q>::c[o][2] * (2.0 * fo + mv);
+            }
+        }
+    }
+    block_reduce_store(acc, partials + (size_t)blockIdx.x * kDiagFields);
+}
+
+// ------------------------------------------------------------ host launchers
+// Instantiated once per storage format in kern_<format>.hip.
+template <int F>
+struct FormatLaunchers {
+    // cells per lane built: up to 4 for 16-bit DDFs, 2 for FP32, 1 for FP64
+    // (two FP64 cells per lane exceed the register file for D3Q27)
+    static constexpr int kMaxCpl = sizeof(typename Codec<F>::T) == 2 ? 4 : (sizeof(typename Codec<F>::T) == 4 ? 2 : 1);
+
+    template <int Q, class A, int COLL, int CPL>
+    static hipError_t single_cpl(const StepLaunch& s, const LatDev& L) {
+        const uint32_t per_wg = (uint32_t)s.block * CPL;
+        const uint32_t segs = (L.nx + per_wg - 1) / per_wg;
+        const uint32_t grid = segs * L.ny * L.nz;
+        hipLaunchKernelGGL((k_step_single<Q, F, A, COLL, CPL>), dim3(grid), dim3(s.block), 0, s.stream, L,
+                           s.parity, segs, s.enc);
+        return hipGetLastError();
+    }
+    template <int Q, class A, int COLL, int CPL>
+    static hipError_t batched_cpl(const StepLaunch& s) {
+        hipLaunchKernelGGL((k_step_batched<Q, F, A, COLL, CPL>), dim3(s.grid), dim3(s.block), 0, s.stream,
+                           s.lats, s.tiles, s.ntiles, s.parity, s.enc);
+        return hipGetLastError();
+    }
+    template <int Q, class A, int COLL>
+    static hipError_t single_qac(const StepLaunch& s, const LatDev& L) {
+        if (s.cpl == 1) return single_cpl<Q, A, COLL, 1>(s, L);
+        if constexpr (kMaxCpl >= 2)
+            if (s.cpl == 2) return single_cpl<Q, A, COLL, 2>(s, L);
+        if constexpr (kMaxCpl >= 4)
+            if (s.cpl == 4) return single_cpl<Q, A, COLL, 4>(s, L);
+        return hipErrorInvalidValue;
+    }
+    template <int Q, class A, int COLL>
+    static hipError_t batched_qac(const StepLaunch& s) {
+        if (s.cpl == 1) return batched_cpl<Q, A, COLL, 1>(s);
+        if constexpr (kMaxCpl >= 2)
+            if (s.cpl == 2) return batched_cpl<Q, A, COLL, 2>(s);
+        if constexpr (kMaxCpl >= 4)
+            if (s.cpl == 4) return batched_cpl<Q, A, COLL, 4>(s);
+        return hipErrorInvalidValue;
+    }
+};
+
+}  // namespace lbm

@@ -1,0 +1,800 @@
+// lbm_runtime.hip -- host runtime behind the C interface of include/lbm.h:
+// handles, device memory, flags pre-pass, launch configuration, HIP graphs,
+// autotuning, encoder tables, diagnostics, codec and copy-probe kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_codecs.h"
+#include "lbm_internal.h"
+#include "lbm_kernels.h"
+
+using namespace lbm;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static lbm_status fail(lbm_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+extern "C" const char* lbm_last_error(void) { return g_err.c_str(); }
+
+#include "lbm_enc_table.h"
+
+static bool uses_table(int storage) { return storage >= S_FP16C && storage <= S_P16_2C; }
+
+static int ddf_bytes(int storage) { return storage == S_FP64 ? 8 : (storage == S_FP32 ? 4 : 2); }
+
+// Per-process device tables of the software encoders (one per format).
+struct EncTables {
+    EncEntry* dev[8] = {nullptr};
+    int device = -1;
+};
+static EncTables g_tables;
+
+static lbm_status device_table(int storage, const EncEntry** out) {
+    *out = nullptr;
+    if (!uses_table(storage)) return LBM_OK;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (g_tables.device != dev) {
+        g_tables = EncTables{};
+        g_tables.device = dev;
+    }
+    if (!g_tables.dev[storage]) {
+        EncEntry host[256];
+        std::string why;
+        if (!build_encoder_table(storage, host, &why))
+            return fail(LBM_EDEVICE, "encoder table of format %d: %s", storage, why.c_str());
+        EncEntry* d = nullptr;
+        HIP_TRY(hipMalloc(&d, sizeof host));
+        HIP_TRY(hipMemcpy(d, host, sizeof host, hipMemcpyHostToDevice));
+        g_tables.dev[storage] = d;
+    }
+    *out = g_tables.dev[storage];
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ dispatch by format
+#define LBM_FORMAT_SWITCH(storage, EXPR_OF)                    \
+    switch (storage) {                                         \
+    case S_FP64: return EXPR_OF(fp64);                         \
+    case S_FP32: return EXPR_OF(fp32);                         \
+    case S_FP16: return EXPR_OF(fp16);                         \
+    case S_FP16S: return EXPR_OF(fp16s);                       \
+    case S_FP16C: return EXPR_OF(fp16c);                       \
+    case S_P16_0S: return EXPR_OF(p16_0s);                     \
+    case S_P16_1S: return EXPR_OF(p16_1s);                     \
+    case S_P16_2C: return EXPR_OF(p16_2c);                     \
+    default: return hipErrorInvalidValue;                      \
+    }
+
+namespace lbm {
+hipError_t launch_step_single(const StepLaunch& s, const LatDev& lat) {
+#define E(N) step_single_##N(s, lat)
+    LBM_FORMAT_SWITCH(s.storage, E)
+#undef E
+}
+hipError_t launch_step_batched(const StepLaunch& s) {
+#define E(N) step_batched_##N(s)
+    LBM_FORMAT_SWITCH(s.storage, E)
+#undef E
+}
+hipError_t launch_init(int q, int storage, int arith, const LatDev& lat, const double* rho, const double* u,
+                       const EncEntry* enc, hipStream_t st) {
+#define E(N) init_##N(q, arith, lat, rho, u, enc, st)
+    LBM_FORMAT_SWITCH(storage, E)
+#undef E
+}
+hipError_t launch_moments(int q, int storage, int arith, const LatDev& lat, int parity, double* rho, double* u,
+                          hipStream_t st) {
+#define E(N) moments_##N(q, arith, lat, parity, rho, u, st)
+    LBM_FORMAT_SWITCH(storage, E)
+#undef E
+}
+}  // namespace lbm
+
+// ------------------------------------------------------------------ small kernels
+__global__ void __launch_bounds__(256) k_diag_finish(const double* __restrict__ partials, int nblocks,
+                                                     double* __restrict__ out) {
+    // one workgroup; thread t owns field t and sums the partials in block order
+    const int t = threadIdx.x;
+    if (t < kDiagFields) {
+        double v = t == kDiagFields - 1 ? 0.0 : 0.0;
+        for (int b = 0; b < nblocks; b++) {
+            const double p = partials[(size_t)b * kDiagFields + t];
+            v = (t == kDiagFields - 1) ? fmax(v, p) : v + p;
+        }
+        out[t] = v;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_encode(int storage, const float* __restrict__ in,
+                                                uint16_t* __restrict__ out, int64_t n,
+                                                const EncEntry* __restrict__ enc) {
+    __shared__ EncEntry s_tab[256];
+    if (enc) {
+        for (int k = threadIdx.x; k < 256; k += blockDim.x) s_tab[k] = enc[k];
+        __syncthreads();
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = in[i];
+        uint16_t c;
+        switch (storage) {
+        case S_FP16: c = Codec<S_FP16>::store<float>(x, nullptr); break;
+        case S_FP16S: c = Codec<S_FP16S>::store<float>(x, nullptr); break;
+        default: c = table_encode(x, s_tab); break;
+        }
+        out[i] = c;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_decode(int storage, const uint16_t* __restrict__ in,
+                                                float* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = decode16(storage, in[i]);
+}
+
+// NEAR bit of every fluid cell with a SOLID cell among its q-1 periodic
+// neighbours; reads the caller's flags from `raw`, writes `out`.
+template <int Q>
+__global__ void __launch_bounds__(256) k_mark_near(const uint8_t* __restrict__ raw, uint8_t* __restrict__ out,
+                                                   uint32_t nx, uint32_t ny, uint32_t nz) {
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    uint8_t f = raw[n];
+    if (!(f & (F_SOLID | F_EQ))) {
+        const uint32_t x = (uint32_t)(n % nx), yz = (uint32_t)(n / nx), y = yz % ny, z = yz / ny;
+        bool near = false;
+        for (int i = 1; i < Q; i++) {
+            const uint32_t sx = (x + nx - VelSet<Q>::c[i][0]) % nx;
+            const uint32_t sy = (y + ny - VelSet<Q>::c[i][1]) % ny;
+            const uint32_t sz = (z + nz - VelSet<Q>::c[i][2]) % nz;
+            near |= (raw[sx + (size_t)nx * (sy + (size_t)ny * sz)] & F_SOLID) != 0;
+        }
+        if (near) f |= F_NEAR;
+    }
+    out[n] = f;
+}
+
+__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ handle
+struct Lattice {
+    lbm_params p{};
+    size_t N = 0;
+    uint32_t plane = 0;
+    void* f[2] = {nullptr, nullptr};
+    uint8_t* flags = nullptr;
+    LatDev dev{};
+};
+
+struct lbm_handle {
+    hipStream_t stream = nullptr;
+    lbm_alloc_fn alloc = nullptr;
+    lbm_free_fn free_ = nullptr;
+    void* ctx = nullptr;
+    int q = 19, storage = 1, arith = 0, collision = 0;
+    std::vector<Lattice> lats;
+    int parity = 0;
+    int64_t step = 0;
+    int64_t device_bytes = 0;
+    int num_cus = 256;
+    lbm_launch launch{};
+    const EncEntry* enc = nullptr;
+    // batched launch
+    LatDev* d_lats = nullptr;
+    Tile* d_tiles = nullptr;
+    uint32_t ntiles = 0;
+    int tiles_block = 0;
+    // graph
+    hipGraphExec_t graph = nullptr;
+    int graph_steps = 0;
+    // diagnostics scratch
+    double* d_partials = nullptr;
+    double* d_out = nullptr;
+};
+
+static void* dev_alloc(lbm_handle* h, size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (h->alloc) p = h->alloc(bytes, h->ctx);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (p) h->device_bytes += (int64_t)bytes;
+    return p;
+}
+static void dev_free(lbm_handle* h, void* p) {
+    if (!p) return;
+    if (h->free_) h->free_(p, h->ctx);
+    else (void)hipFree(p);
+}
+
+static void drop_graph(lbm_handle* h) {
+    if (h->graph) {
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    h->graph_steps = 0;
+}
+
+static void fill_dev(Lattice& L, int arith) {
+    (void)arith;
+    LatDev& d = L.dev;
+    d.f[0] = L.f[0];
+    d.f[1] = L.f[1];
+    d.flags = L.flags;
+    d.nx = (uint32_t)L.p.nx;
+    d.ny = (uint32_t)L.p.ny;
+    d.nz = (uint32_t)L.p.nz;
+    d.plane = L.plane;
+    d.omega = 1.0 / L.p.tau;
+    d.omega_m = 1.0 / (0.5 + L.p.trt_magic / (L.p.tau - 0.5));
+    for (int a = 0; a < 3; a++) {
+        d.force[a] = L.p.force[a];
+        d.wall_u[a] = L.p.wall_u[a];
+        d.eq_u[a] = L.p.eq_u[a];
+    }
+    d.eq_rho = L.p.eq_rho;
+    d.forced = (L.p.force[0] != 0.0 || L.p.force[1] != 0.0 || L.p.force[2] != 0.0) ? 1 : 0;
+}
+
+static lbm_status check_params(const lbm_params& p, int k) {
+    if (p.q != 19 && p.q != 27) return fail(LBM_EINVAL, "lattice %d: q must be 19 or 27", k);
+    if (p.collision != LBM_SRT && p.collision != LBM_TRT) return fail(LBM_EINVAL, "lattice %d: unknown collision", k);
+    if (p.storage < LBM_FP64 || p.storage > LBM_P16_2C) return fail(LBM_EINVAL, "lattice %d: unknown storage", k);
+    if (p.arith != LBM_ARITH_FP32 && p.arith != LBM_ARITH_FP64) return fail(LBM_EINVAL, "lattice %d: unknown arith", k);
+    if (p.reserved != 0) return fail(LBM_EINVAL, "lattice %d: reserved field must be 0", k);
+    if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return fail(LBM_EINVAL, "lattice %d: tau must be > 0.5", k);
+    if (p.collision == LBM_TRT && !(p.trt_magic > 0.0)) return fail(LBM_EINVAL, "lattice %d: trt_magic must be > 0", k);
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nx > 65535 || p.ny > 65535 || p.nz > 65535)
+        return fail(LBM_EINVAL, "lattice %d: sizes must be in [1, 65535]", k);
+    const double N = (double)p.nx * p.ny * p.nz;
+    if (N >= 2147483648.0 || N * ddf_bytes(p.storage) >= 4294967296.0)
+        return fail(LBM_EINVAL, "lattice %d: too many cells for 32-bit per-plane offsets", k);
+    if (p.arith == LBM_ARITH_FP64 && p.storage != LBM_FP64 && p.storage != LBM_FP32)
+        return fail(LBM_EUNSUPPORTED, "lattice %d: FP64 arithmetic needs FP64 or FP32 storage", k);
+    if (p.arith == LBM_ARITH_FP32 && p.storage == LBM_FP64)
+        return fail(LBM_EUNSUPPORTED, "lattice %d: FP64 storage is built with FP64 arithmetic only", k);
+    return LBM_OK;
+}
+
+static lbm_status run_init(lbm_handle* h, Lattice& L, const double* d_rho, const double* d_u) {
+    HIP_TRY(launch_init(h->q, h->storage, h->arith, L.dev, d_rho, d_u, h->enc, h->stream));
+    return LBM_OK;
+}
+
+static lbm_status rebuild_tiles(lbm_handle* h);
+
+extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, void* stream,
+                                 lbm_alloc_fn alloc, lbm_free_fn free_, void* alloc_ctx, lbm_handle** out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || n_lattices < 1 || n_lattices > 65535) return fail(LBM_EINVAL, "need 1..65535 lattices");
+    if ((alloc == nullptr) != (free_ == nullptr)) return fail(LBM_EINVAL, "alloc and free_ go together");
+    for (int k = 0; k < n_lattices; k++) {
+        lbm_status st = check_params(params[k], k);
+        if (st != LBM_OK) return st;
+        const lbm_params& a = params[0];
+        const lbm_params& b = params[k];
+        if (a.q != b.q || a.collision != b.collision || a.storage != b.storage || a.arith != b.arith)
+            return fail(LBM_EUNSUPPORTED, "lattice %d: q, collision, storage and arith must match lattice 0", k);
+    }
+    lbm_handle* h = new (std::nothrow) lbm_handle();
+    if (!h) return fail(LBM_ENOMEM, "out of host memory");
+    h->stream = (hipStream_t)stream;
+    h->alloc = alloc;
+    h->free_ = free_;
+    h->ctx = alloc_ctx;
+    h->q = params[0].q;
+    h->storage = params[0].storage;
+    h->arith = params[0].arith;
+    h->collision = params[0].collision;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete h;
+        return fail(LBM_EDEVICE, "no HIP device");
+    }
+    h->num_cus = prop.multiProcessorCount;
+    h->launch = {n_lattices > 1 ? LBM_LAUNCH_BATCHED : LBM_LAUNCH_PER_LATTICE, 256, 1, 0, 0};
+    lbm_status st = device_table(h->storage, &h->enc);
+    if (st != LBM_OK) { delete h; return st; }
+    const int b = ddf_bytes(h->storage);
+    h->lats.resize(n_lattices);
+    for (int k = 0; k < n_lattices; k++) {
+        Lattice& L = h->lats[k];
+        L.p = params[k];
+        L.N = (size_t)L.p.nx * L.p.ny * L.p.nz;
+        L.plane = (uint32_t)((L.N + 127) / 128 * 128);     // 256-byte aligned planes
+        const size_t bytes = (size_t)L.plane * h->q * b;
+        L.f[0] = dev_alloc(h, bytes);
+        L.f[1] = dev_alloc(h, bytes);
+        L.flags = (uint8_t*)dev_alloc(h, L.N);
+        if (!L.f[0] || !L.f[1] || !L.flags) {
+            lbm_destroy(h);
+            return fail(LBM_ENOMEM, "device allocation of lattice %d (%zu bytes per buffer) failed", k, bytes);
+        }
+        if (hipMemsetAsync(L.flags, 0, L.N, h->stream) != hipSuccess ||
+            hipMemsetAsync(L.f[0], 0, bytes, h->stream) != hipSuccess ||
+            hipMemsetAsync(L.f[1], 0, bytes, h->stream) != hipSuccess) {
+            lbm_destroy(h);
+            return fail(LBM_EDEVICE, "hipMemsetAsync failed");
+        }
+        fill_dev(L, h->arith);
+        st = run_init(h, L, nullptr, nullptr);
+        if (st != LBM_OK) { lbm_destroy(h); return st; }
+    }
+    h->d_partials = (double*)dev_alloc(h, sizeof(double) * kDiagBlocks * kDiagFields);
+    h->d_out = (double*)dev_alloc(h, sizeof(double) * kDiagFields);
+    h->d_lats = (LatDev*)dev_alloc(h, sizeof(LatDev) * n_lattices);
+    if (!h->d_partials || !h->d_out || !h->d_lats) {
+        lbm_destroy(h);
+        return fail(LBM_ENOMEM, "device allocation failed");
+    }
+    std::vector<LatDev> descs(n_lattices);
+    for (int k = 0; k < n_lattices; k++) descs[k] = h->lats[k].dev;
+    if (hipMemcpyAsync(h->d_lats, descs.data(), sizeof(LatDev) * n_lattices, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+        lbm_destroy(h);
+        return fail(LBM_EDEVICE, "descriptor upload failed");
+    }
+    st = rebuild_tiles(h);
+    if (st != LBM_OK) { lbm_destroy(h); return st; }
+    *out = h;
+    return LBM_OK;
+}
+
+extern "C" void lbm_destroy(lbm_handle* h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    for (auto& L : h->lats) {
+        dev_free(h, L.f[0]);
+        dev_free(h, L.f[1]);
+        dev_free(h, L.flags);
+    }
+    dev_free(h, h->d_partials);
+    dev_free(h, h->d_out);
+    dev_free(h, h->d_lats);
+    dev_free(h, h->d_tiles);
+    delete h;
+}
+
+static lbm_status check_lattice(lbm_handle* h, int32_t k) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (k < 0 || k >= (int)h->lats.size()) return fail(LBM_EINVAL, "lattice index %d out of range", k);
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ tiles
+// Tile table of the batched launch for the current block size: row segments
+// of `block` cells, lattice by lattice, row by row.
+static lbm_status rebuild_tiles(lbm_handle* h) {
+    const int T = h->launch.block * h->launch.cells_per_lane;
+    if (h->d_tiles && h->tiles_block == T) return LBM_OK;
+    std::vector<Tile> tiles;
+    for (size_t k = 0; k < h->lats.size(); k++) {
+        const lbm_params& p = h->lats[k].p;
+        for (int z = 0; z < p.nz; z++)
+            for (int y = 0; y < p.ny; y++)
+                for (int x0 = 0; x0 < p.nx; x0 += T)
+                    tiles.push_back(Tile{(uint16_t)k, (uint16_t)x0, (uint16_t)y, (uint16_t)z});
+    }
+    if (tiles.size() >= 0xFFFFFFFFull) return fail(LBM_EINVAL, "too many tiles");
+    dev_free(h, h->d_tiles);
+    h->d_tiles = (Tile*)dev_alloc(h, sizeof(Tile) * tiles.size());
+    if (!h->d_tiles) return fail(LBM_ENOMEM, "tile table allocation failed");
+    HIP_TRY(hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->ntiles = (uint32_t)tiles.size();
+    h->tiles_block = T;
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ stepping
+static StepLaunch make_launch(lbm_handle* h, const lbm_launch& cfg, int parity) {
+    StepLaunch s{};
+    s.q = h->q;
+    s.storage = h->storage;
+    s.arith = h->arith;
+    s.collision = h->collision;
+    s.block = cfg.block;
+    s.cpl = cfg.cells_per_lane;
+    s.parity = parity;
+    s.lats = h->d_lats;
+    s.tiles = h->d_tiles;
+    s.ntiles = h->ntiles;
+    s.grid = cfg.persistent > 0 ? (uint32_t)std::min<int64_t>((int64_t)cfg.persistent * h->num_cus, h->ntiles)
+                                : h->ntiles;
+    s.enc = h->enc;
+    s.stream = h->stream;
+    return s;
+}
+
+// Enqueue one time step with the given configuration, reading buffer `parity`.
+static hipError_t enqueue_step(lbm_handle* h, const lbm_launch& cfg, int parity) {
+    const StepLaunch s = make_launch(h, cfg, parity);
+    if (cfg.mode == LBM_LAUNCH_BATCHED) return launch_step_batched(s);
+    for (auto& L : h->lats) {
+        hipError_t e = launch_step_single(s, L.dev);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static lbm_status ensure_graph(lbm_handle* h) {
+    const int K = h->launch.graph_steps;
+    if (K <= 0 || (h->graph && h->graph_steps == K)) return LBM_OK;
+    drop_graph(h);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < K && e == hipSuccess; s++) e = enqueue_step(h, h->launch, s & 1);
+    hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(LBM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    h->graph = ex;
+    h->graph_steps = K;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step(lbm_handle* h, int64_t n) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "n_steps must be >= 0");
+    lbm_status st = ensure_graph(h);
+    if (st != LBM_OK) return st;
+    const int K = h->graph ? h->graph_steps : 0;
+    while (n > 0) {
+        if (K > 0 && h->parity == 0 && n >= K) {
+            HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+            n -= K;
+            h->step += K;       // K is even: parity unchanged
+            continue;
+        }
+        HIP_TRY(enqueue_step(h, h->launch, h->parity));
+        h->parity ^= 1;
+        h->step += 1;
+        n -= 1;
+    }
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ boundaries and state
+extern "C" lbm_status lbm_set_boundaries(lbm_handle* h, int32_t k, const uint8_t* flags) {
+    lbm_status st = check_lattice(h, k);
+    if (st != LBM_OK) return st;
+    if (!flags) return fail(LBM_EINVAL, "flags is NULL");
+    Lattice& L = h->lats[k];
+    std::vector<uint8_t> fl(L.N);
+    for (size_t n = 0; n < L.N; n++) {
+        const uint8_t f = flags[n];
+        if (f & ~(LBM_FLAG_SOLID | LBM_FLAG_EQ | LBM_FLAG_MOVING))
+            return fail(LBM_EINVAL, "cell %zu: unknown flag bits 0x%x", n, f);
+        if ((f & LBM_FLAG_MOVING) && !(f & LBM_FLAG_SOLID))
+            return fail(LBM_EINVAL, "cell %zu: MOVING without SOLID", n);
+        if ((f & LBM_FLAG_EQ) && (f & LBM_FLAG_SOLID))
+            return fail(LBM_EINVAL, "cell %zu: EQ together with SOLID", n);
+        fl[n] = f;
+    }
+    // NEAR (fluid cell with a SOLID cell among its q-1 neighbours) is marked on
+    // the device from a staging copy of the caller's flags.
+    uint8_t* d_raw = (uint8_t*)dev_alloc(h, L.N);
+    if (!d_raw) return fail(LBM_ENOMEM, "flags staging buffer");
+    hipError_t e = hipMemcpyAsync(d_raw, fl.data(), L.N, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+        const dim3 grid((unsigned)((L.N + 255) / 256));
+        if (h->q == 19)
+            hipLaunchKernelGGL(k_mark_near<19>, grid, dim3(256), 0, h->stream, d_raw, L.flags, L.dev.nx, L.dev.ny, L.dev.nz);
+        else
+            hipLaunchKernelGGL(k_mark_near<27>, grid, dim3(256), 0, h->stream, d_raw, L.flags, L.dev.nx, L.dev.ny, L.dev.nz);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // fl is a local buffer
+    dev_free(h, d_raw);
+    h->device_bytes -= (int64_t)L.N;
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "flag upload failed: %s", hipGetErrorString(e));
+    drop_graph(h);
+    st = run_init(h, L, nullptr, nullptr);
+    if (st != LBM_OK) return st;
+    h->step = 0;
+    return LBM_OK;
+}
+
+// The initialisation writes both buffers, so the current parity stays valid.
+extern "C" lbm_status lbm_set_rho_u(lbm_handle* h, int32_t k, const double* rho, const double* u) {
+    lbm_status st = check_lattice(h, k);
+    if (st != LBM_OK) return st;
+    Lattice& L = h->lats[k];
+    double* d_rho = nullptr;
+    double* d_u = nullptr;
+    if (rho) {
+        if (hipMalloc(&d_rho, L.N * sizeof(double)) != hipSuccess) return fail(LBM_ENOMEM, "rho upload buffer");
+        HIP_TRY(hipMemcpyAsync(d_rho, rho, L.N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    }
+    if (u) {
+        if (hipMalloc(&d_u, 3 * L.N * sizeof(double)) != hipSuccess) {
+            (void)hipFree(d_rho);
+            return fail(LBM_ENOMEM, "u upload buffer");
+        }
+        HIP_TRY(hipMemcpyAsync(d_u, u, 3 * L.N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    }
+    st = run_init(h, L, d_rho, d_u);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d_rho);
+    (void)hipFree(d_u);
+    if (st != LBM_OK) return st;
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "initialisation failed: %s", hipGetErrorString(e));
+    h->step = 0;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_get_rho_u(lbm_handle* h, int32_t k, double* rho, double* u) {
+    lbm_status st = check_lattice(h, k);
+    if (st != LBM_OK) return st;
+    Lattice& L = h->lats[k];
+    double* d = nullptr;
+    if (hipMalloc(&d, 4 * L.N * sizeof(double)) != hipSuccess) return fail(LBM_ENOMEM, "moments buffer");
+    hipError_t e = launch_moments(h->q, h->storage, h->arith, L.dev, h->parity, d, d + L.N, h->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d, L.N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u, d + L.N, 3 * L.N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "moments failed: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_ddf(lbm_handle* h, int32_t k, const void* host) {
+    lbm_status st = check_lattice(h, k);
+    if (st != LBM_OK) return st;
+    if (!host) return fail(LBM_EINVAL, "host buffer is NULL");
+    Lattice& L = h->lats[k];
+    const size_t b = ddf_bytes(h->storage);
+    for (int i = 0; i < h->q; i++)
+        HIP_TRY(hipMemcpyAsync((char*)L.f[h->parity] + (size_t)i * L.plane * b, (const char*)host + (size_t)i * L.N * b,
+                               L.N * b, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_get_ddf(lbm_handle* h, int32_t k, void* host) {
+    lbm_status st = check_lattice(h, k);
+    if (st != LBM_OK) return st;
+    if (!host) return fail(LBM_EINVAL, "host buffer is NULL");
+    Lattice& L = h->lats[k];
+    const size_t b = ddf_bytes(h->storage);
+    for (int i = 0; i < h->q; i++)
+        HIP_TRY(hipMemcpyAsync((char*)host + (size_t)i * L.N * b, (const char*)L.f[h->parity] + (size_t)i * L.plane * b,
+                               L.N * b, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_ref, lbm_diag* out) {
+    lbm_status st = check_lattice(h, k);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    Lattice& L = h->lats[k];
+    double* d_ref = nullptr;
+    if (u_ref) {
+        if (hipMalloc(&d_ref, 3 * L.N * sizeof(double)) != hipSuccess) return fail(LBM_ENOMEM, "u_ref buffer");
+        hipError_t e = hipMemcpyAsync(d_ref, u_ref, 3 * L.N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) { (void)hipFree(d_ref); return fail(LBM_EDEVICE, "u_ref upload failed"); }
+    }
+    double res[kDiagFields];
+    hipError_t e;
+#define E(N) diag_##N(h->q, h->arith, L.dev, h->parity, d_ref, h->d_partials, kDiagBlocks, h->stream)
+    switch (h->storage) {
+    case S_FP64: e = E(fp64); break;
+    case S_FP32: e = E(fp32); break;
+    case S_FP16: e = E(fp16); break;
+    case S_FP16S: e = E(fp16s); break;
+    case S_FP16C: e = E(fp16c); break;
+    case S_P16_0S: e = E(p16_0s); break;
+    case S_P16_1S: e = E(p16_1s); break;
+    default: e = E(p16_2c); break;
+    }
+#undef E
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(64), 0, h->stream, h->d_partials, kDiagBlocks, h->d_out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(res, h->d_out, sizeof res, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d_ref);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "diagnostics failed: %s", hipGetErrorString(e));
+    out->mass = res[0];
+    out->momentum[0] = res[1];
+    out->momentum[1] = res[2];
+    out->momentum[2] = res[3];
+    out->kinetic_energy = res[4];
+    out->l2_error = u_ref ? (res[6] > 0 ? std::sqrt(res[5] / res[6]) : 0.0) : -1.0;
+    out->force_on_solid[0] = res[7];
+    out->force_on_solid[1] = res[8];
+    out->force_on_solid[2] = res[9];
+    out->nonfinite_cells = (int64_t)res[10];
+    out->u_max = res[11];
+    out->step = h->step;
+    if (out->nonfinite_cells > 0)
+        return fail(LBM_ENONFINITE, "lattice %d: %lld fluid cells with non-finite fields", k,
+                    (long long)out->nonfinite_cells);
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ launch configuration
+static lbm_status check_launch(lbm_handle* h, const lbm_launch& c) {
+    if (c.mode != LBM_LAUNCH_PER_LATTICE && c.mode != LBM_LAUNCH_BATCHED) return fail(LBM_EINVAL, "unknown launch mode");
+    if (c.block != 64 && c.block != 128 && c.block != 256 && c.block != 512) return fail(LBM_EINVAL, "block must be 64..512");
+    if (c.cells_per_lane != 1 && c.cells_per_lane != 2 && c.cells_per_lane != 4)
+        return fail(LBM_EINVAL, "cells_per_lane must be 1, 2 or 4");
+    if (c.cells_per_lane == 4 && ddf_bytes(h->storage) != 2)
+        return fail(LBM_EUNSUPPORTED, "cells_per_lane 4 needs 16-bit storage");
+    if (c.cells_per_lane > 1 && ddf_bytes(h->storage) == 8)
+        return fail(LBM_EUNSUPPORTED, "FP64 storage runs one cell per lane");
+    for (size_t k = 0; k < h->lats.size(); k++)
+        if (h->lats[k].p.nx % c.cells_per_lane)
+            return fail(LBM_EINVAL, "lattice %zu: nx = %d is not a multiple of cells_per_lane", k,
+                        h->lats[k].p.nx);
+    if (c.persistent < 0 || c.persistent > 64) return fail(LBM_EINVAL, "persistent must be in [0, 64]");
+    if (c.graph_steps < 0 || (c.graph_steps & 1) || c.graph_steps > 100000)
+        return fail(LBM_EINVAL, "graph_steps must be even and >= 0");
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_launch(lbm_handle* h, const lbm_launch* cfg) {
+    if (!h || !cfg) return fail(LBM_EINVAL, "NULL argument");
+    lbm_status st = check_launch(h, *cfg);
+    if (st != LBM_OK) return st;
+    drop_graph(h);
+    h->launch = *cfg;
+    return rebuild_tiles(h);
+}
+
+extern "C" lbm_status lbm_get_launch(lbm_handle* h, lbm_launch* cfg) {
+    if (!h || !cfg) return fail(LBM_EINVAL, "NULL argument");
+    *cfg = h->launch;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launch* best) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (trial_steps < 1) return fail(LBM_EINVAL, "trial_steps must be >= 1");
+    const lbm_launch keep = h->launch;
+    std::vector<lbm_launch> cands;
+    const int blocks[] = {64, 128, 256, 512};
+    for (int cpl : {1, 2, 4}) {
+        for (int b : blocks) {
+            const lbm_launch c{LBM_LAUNCH_PER_LATTICE, b, cpl, 0, keep.graph_steps};
+            if (check_launch(h, c) != LBM_OK) continue;
+            cands.push_back(c);
+            if (h->lats.size() > 1) {
+                cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, 0, keep.graph_steps});
+                for (int pers : {2, 4, 8}) cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, pers, keep.graph_steps});
+            }
+        }
+    }
+    g_err.clear();
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    lbm_launch best_cfg = keep;
+    for (const lbm_launch& c : cands) {
+        h->launch = c;
+        lbm_status st = rebuild_tiles(h);
+        if (st != LBM_OK) break;
+        // warm-up, then time; always reading the current buffer
+        hipError_t e = enqueue_step(h, c, h->parity);
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        for (int s = 0; s < trial_steps && e == hipSuccess; s++) e = enqueue_step(h, c, h->parity);
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            h->launch = keep;
+            rebuild_tiles(h);
+            return fail(LBM_EDEVICE, "autotune launch failed: %s", hipGetErrorString(e));
+        }
+        // ties go to the smaller workgroup (candidates are in increasing size)
+        if (ms < best_ms * 0.995f) {
+            best_ms = ms;
+            best_cfg = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    drop_graph(h);
+    h->launch = best_cfg;
+    lbm_status st = rebuild_tiles(h);
+    if (st != LBM_OK) return st;
+    if (best) *best = best_cfg;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_info_get(lbm_handle* h, lbm_info* out) {
+    if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+    int64_t cells = 0;
+    for (auto& L : h->lats) cells += (int64_t)L.N;
+    out->cells = cells;
+    out->device_bytes = h->device_bytes;
+    out->n_lattices = (int32_t)h->lats.size();
+    out->bytes_per_ddf = ddf_bytes(h->storage);
+    out->step = h->step;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_synchronize(lbm_handle* h) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ codecs and probe
+extern "C" lbm_status lbm_encode(int32_t storage, const float* d_in, uint16_t* d_out, int64_t n, void* stream) {
+    if (storage < LBM_FP16 || storage > LBM_P16_2C) return fail(LBM_EINVAL, "not a 16-bit format");
+    if (n < 0 || (n > 0 && (!d_in || !d_out))) return fail(LBM_EINVAL, "bad arguments");
+    if (n == 0) return LBM_OK;
+    const EncEntry* enc = nullptr;
+    lbm_status st = device_table(storage, &enc);
+    if (st != LBM_OK) return st;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_encode, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, storage, d_in, d_out, n, enc);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_decode(int32_t storage, const uint16_t* d_in, float* d_out, int64_t n, void* stream) {
+    if (storage < LBM_FP16 || storage > LBM_P16_2C) return fail(LBM_EINVAL, "not a 16-bit format");
+    if (n < 0 || (n > 0 && (!d_in || !d_out))) return fail(LBM_EINVAL, "bad arguments");
+    if (n == 0) return LBM_OK;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, storage, d_in, d_out, n);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_copy_probe(const void* d_src, void* d_dst, size_t bytes, void* stream) {
+    if (!d_src || !d_dst || (bytes % 16) || ((uintptr_t)d_src % 16) || ((uintptr_t)d_dst % 16))
+        return fail(LBM_EINVAL, "copy probe needs 16-byte aligned pointers and size");
+    const size_t n = bytes / 16;
+    if (n == 0) return LBM_OK;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (const float4*)d_src,
+                       (float4*)d_dst, n);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
