@@ -120,7 +120,8 @@ typedef struct {
                                 grid walking the tile table; 0 = one workgroup
                                 per tile */
     int32_t graph_steps;     /* > 0 (even): lbm_step replays a HIP graph of
-                                this many steps; 0 = direct launches */
+                                this many steps (needs a non-null stream);
+                                0 = direct launches */
 } lbm_launch;
 
 typedef struct {

@@ -267,12 +267,13 @@ def lbm_copy_probe(d_src: int, d_dst: int, nbytes: int, stream=None):
 # ----------------------------------------------------------------- convenience wrapper
 class Lattices:
     """One handle: n lattices sharing velocity set, collision, storage and
-    arithmetic.  `stream` defaults to torch's current stream; device memory
-    comes from torch's caching allocator unless torch_alloc=False."""
+    arithmetic.  `stream` defaults to a new torch stream of default priority
+    (HIP graphs cannot be captured on the null stream); device memory comes
+    from torch's caching allocator unless torch_alloc=False."""
 
     def __init__(self, params, stream=None, torch_alloc: bool = True):
         self.params = [params] if isinstance(params, LbmParams) else list(params)
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = stream if stream is not None else torch.cuda.Stream()
         self._alloc = _TorchAllocator(self.stream) if torch_alloc else None
         self.h = lbm_create(self.params, self.stream, self._alloc)
         self.q = self.params[0].q

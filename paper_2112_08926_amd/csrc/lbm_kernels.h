@@ -426,7 +426,6 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
     const uint32_t nx = L.nx;
     const uint32_t x = x0 + threadIdx.x * CPL;
     if (x >= nx) return;
-    const uint32_t lane = threadIdx.x & 63;
     RowCtx rc;
     make_rows(L, y, z, rc);
     const uint32_t row = rc.rows[4];
@@ -443,10 +442,16 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
     const T* __restrict__ src = (const T*)L.f[parity];
     T* __restrict__ dst = (T*)L.f[parity ^ 1];
     const size_t plane = L.plane;
-    const bool first_lane = lane == 0;
-    const bool last_lane = lane == 63 || x + CPL == nx;
-    const uint32_t xm = x == 0 ? nx - 1 : x - 1;
-    const uint32_t xn = x + CPL == nx ? 0 : x + CPL;
+    // The elements just outside this wavefront's span of the row: before its
+    // first lane and after its last active lane (periodic wrap).  Both indices
+    // are wavefront-uniform, so every lane loads the same address (no
+    // divergent branch) and only the edge lane keeps the value.
+    const uint32_t xw0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+    const uint32_t xw_end = min(xw0 + 64u * CPL, nx);
+    const uint32_t xm = xw0 == 0 ? nx - 1 : xw0 - 1;
+    const uint32_t xn = xw_end == nx ? 0 : xw_end;
+    const bool first_lane = x == xw0;
+    const bool last_lane = x + CPL == xw_end;
 
     RV raw[Q];
 #pragma unroll
@@ -454,13 +459,13 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
         const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
         const RV v = vload<T, CPL>(p + x);
         if (VelSet<Q>::c[i][0] > 0) {
-            T prev = shfl_elem_up<T>(velem<T, CPL>(v, CPL - 1));
-            if (first_lane) prev = p[xm];
-            raw[i] = shift_up<T, CPL>(v, prev);
+            const T edge = p[xm];
+            const T prev = shfl_elem_up<T>(velem<T, CPL>(v, CPL - 1));
+            raw[i] = shift_up<T, CPL>(v, first_lane ? edge : prev);
         } else if (VelSet<Q>::c[i][0] < 0) {
-            T next = shfl_elem_down<T>(velem<T, CPL>(v, 0));
-            if (last_lane) next = p[xn];
-            raw[i] = shift_down<T, CPL>(v, next);
+            const T edge = p[xn];
+            const T next = shfl_elem_down<T>(velem<T, CPL>(v, 0));
+            raw[i] = shift_down<T, CPL>(v, last_lane ? edge : next);
         } else {
             raw[i] = v;
         }

@@ -669,6 +669,8 @@ static lbm_status check_launch(lbm_handle* h, const lbm_launch& c) {
     if (c.persistent < 0 || c.persistent > 64) return fail(LBM_EINVAL, "persistent must be in [0, 64]");
     if (c.graph_steps < 0 || (c.graph_steps & 1) || c.graph_steps > 100000)
         return fail(LBM_EINVAL, "graph_steps must be even and >= 0");
+    if (c.graph_steps > 0 && h->stream == nullptr)
+        return fail(LBM_EINVAL, "HIP graphs need a non-null stream (the null stream cannot be captured)");
     return LBM_OK;
 }
 
