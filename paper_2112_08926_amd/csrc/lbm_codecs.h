@@ -129,8 +129,11 @@ template <> struct Codec<S_FP16S> {
     using T = uint16_t;
     static constexpr bool kTable = false;
     template <class A> __device__ __forceinline__ static A load(T v) { return half_decode(v) * 0x1p-15f; }
+    // The sign bit is copied explicitly: the compiler fuses the scale and the
+    // conversion into one multiply-add with a +0 addend, which would turn -0
+    // into +0.
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) {
-        return half_encode(v * 32768.0f);
+        return (T)(half_encode(v * 32768.0f) | ((f2u(v) >> 16) & 0x8000u));
     }
 };
 template <> struct Codec<S_FP16C> {

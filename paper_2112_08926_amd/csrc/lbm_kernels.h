@@ -115,6 +115,19 @@ __device__ __forceinline__ uint32_t src_x(int i, uint32_t x, uint32_t xm, uint32
 }
 
 // ------------------------------------------------------------ pull with bounce-back
+// Element `idx` of a row/plane at a wavefront-uniform base: the byte offset
+// is formed in 32 bits so that the load/store can use a scalar 64-bit base
+// plus a 32-bit per-lane offset (no 64-bit address arithmetic per lane).
+// Every offset here is below 2^32 bytes (N * bytes per DDF < 2^32).
+template <class T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t idx) {
+    return *(const T*)((const char*)base + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ void st_off(T* base, uint32_t idx, T v) {
+    *(T*)((char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))) = v;
+}
+
 template <int Q, int F, class A>
 __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
                                      const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp,
@@ -124,7 +137,7 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
-        f[i] = Codec<F>::template load<A>(p[src_x<Q>(i, x, xm, xp)]);
+        f[i] = Codec<F>::template load<A>(ld_off(p, src_x<Q>(i, x, xm, xp)));
     }
     if (__any(near)) {
         // A wall source hands back what this cell sent towards it last step.
@@ -132,7 +145,7 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
         for (int i = 1; i < Q; i++) {
             const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
             if (near && (fs & F_SOLID)) {
-                A v = Codec<F>::template load<A>(src[(size_t)opp(i) * plane + n]);
+                A v = Codec<F>::template load<A>(ld_off(src + (size_t)opp(i) * plane, n));
                 if (fs & F_MOVING) {
                     const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                      VelSet<Q>::c[i][2] * L.wall_u[2]);
@@ -165,7 +178,19 @@ __device__ __forceinline__ void fields(const A (&f)[Q], A& rho, A (&j)[3]) {
 }
 
 // ------------------------------------------------------------ collision
+// Fused multiply-add in the arithmetic precision (__builtin_fma alone would
+// promote float operands to double).
+template <class A> __device__ __forceinline__ A fmaa(A a, A b, A c) {
+    if constexpr (sizeof(A) == 4) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
 // Computes the post-collision DDFs fo[] of one cell from the pulled f[].
+// Opposite directions i, i+1 share B (with opposite sign) and B^2 + C.
+// SRT evaluates each f^eq in the paper's three-FMA order and collides with
+// one FMA.  TRT needs only the pair sums and differences of f^eq, which
+// have the closed forms  feq_i + feq_j = w rho (B^2 + C) + 2 w (rho - 1)
+// and  feq_i - feq_j = 2 w rho B.
 // EXACT_DIV: u = j / rho as the paper's listing divides (FP32/FP64 storage,
 // where the division's rounding is visible); otherwise j * (1/rho), whose
 // extra rounding (1e-7 relative) is far below a 16-bit storage step.
@@ -196,49 +221,55 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
     const A u3x = (A)3 * ux, u3y = (A)3 * uy, u3z = (A)3 * uz;
     const A w = (A)L.omega, wm = (A)L.omega_m;
     const A uF = ux * Fx + uy * Fy + uz * Fz;
+    const A w0 = (A)VelSet<Q>::w(0);
+    const A feq0 = fmaa(w0 * rho, (A)0.5 * C, w0 * rhom1);
 
-    A feq[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        const A wi = (A)VelSet<Q>::w(i);
-        const A B = cdot_i<Q, A>(i, u3x, u3y, u3z);
-        feq[i] = __builtin_fma(wi * rho, __builtin_fma((A)0.5, __builtin_fma(B, B, C), B), wi * rhom1);
-    }
     if (COLL == 0) {
         const A omw = (A)1 - w;
+        const A pre = (A)1 - (A)0.5 * w;
+        fo[0] = fmaa(omw, f[0], w * feq0);
+        if (forced) fo[0] += pre * (w0 * ((A)(-3) * uF));
 #pragma unroll
-        for (int i = 0; i < Q; i++) fo[i] = __builtin_fma(omw, f[i], w * feq[i]);
-        if (forced) {
-            const A pre = (A)1 - (A)0.5 * w;
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                const A wi = (A)VelSet<Q>::w(i);
+        for (int i = 1; i < Q; i += 2) {
+            const A wi = (A)VelSet<Q>::w(i);
+            const A B = cdot_i<Q, A>(i, u3x, u3y, u3z);
+            const A t = fmaa(B, B, C);
+            const A ei = fmaa(wi * rho, fmaa((A)0.5, t, B), wi * rhom1);
+            const A ej = fmaa(wi * rho, fmaa((A)0.5, t, -B), wi * rhom1);
+            fo[i] = fmaa(omw, f[i], w * ei);
+            fo[i + 1] = fmaa(omw, f[i + 1], w * ej);
+            if (forced) {
                 const A cF = cdot_i<Q, A>(i, Fx, Fy, Fz);
                 const A cu = cdot_i<Q, A>(i, ux, uy, uz);
                 const A sym = wi * ((A)9 * cu * cF - (A)3 * uF);
                 const A anti = wi * (A)3 * cF;
                 fo[i] += pre * (sym + anti);
+                fo[i + 1] += pre * (sym - anti);
             }
         }
     } else {
-        fo[0] = f[0] - w * (f[0] - feq[0]);
+        const A hw = (A)0.5 * w, hwm = (A)0.5 * wm;
+        const A prep = (A)1 - hw, prem = (A)1 - hwm;
+        fo[0] = fmaa(-w, f[0] - feq0, f[0]);
+        if (forced) fo[0] += prep * (w0 * ((A)(-3) * uF));
 #pragma unroll
         for (int i = 1; i < Q; i += 2) {
-            const A fp = (A)0.5 * (f[i] + f[i + 1]), fm = (A)0.5 * (f[i] - f[i + 1]);
-            const A ep = (A)0.5 * (feq[i] + feq[i + 1]), em = (A)0.5 * (feq[i] - feq[i + 1]);
-            fo[i] = f[i] - w * (fp - ep) - wm * (fm - em);
-            fo[i + 1] = f[i + 1] - w * (fp - ep) + wm * (fm - em);
-        }
-        if (forced) {
-            const A prep = (A)1 - (A)0.5 * w, prem = (A)1 - (A)0.5 * wm;
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                const A wi = (A)VelSet<Q>::w(i);
+            const A wi = (A)VelSet<Q>::w(i);
+            const A B = cdot_i<Q, A>(i, u3x, u3y, u3z);
+            const A wr = wi * rho;
+            const A esum = fmaa(wr, fmaa(B, B, C), (A)2 * wi * rhom1);
+            const A edif = (A)2 * wr * B;
+            const A s = (f[i] + f[i + 1]) - esum;
+            const A d = (f[i] - f[i + 1]) - edif;
+            fo[i] = fmaa(-hw, s, fmaa(-hwm, d, f[i]));
+            fo[i + 1] = fmaa(-hw, s, fmaa(hwm, d, f[i + 1]));
+            if (forced) {
                 const A cF = cdot_i<Q, A>(i, Fx, Fy, Fz);
                 const A cu = cdot_i<Q, A>(i, ux, uy, uz);
                 const A sym = wi * ((A)9 * cu * cF - (A)3 * uF);
                 const A anti = wi * (A)3 * cF;
                 fo[i] += prep * sym + prem * anti;
+                fo[i + 1] += prep * sym - prem * anti;
             }
         }
     }
@@ -268,7 +299,7 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         T* p = dst + ((size_t)i * plane + rc.rows[4]);
-        p[x] = Codec<F>::template store<A>(fo[i], tab);
+        st_off(p, x, Codec<F>::template store<A>(fo[i], tab));
     }
 }
 
@@ -587,7 +618,7 @@ __global__ void __launch_bounds__(256) k_init(LatDev L, const double* __restrict
     for (int i = 0; i < Q; i++) {
         const A wi = (A)VelSet<Q>::w(i);
         const A B = (A)3 * cdot_i<Q, A>(i, ux, uy, uz);
-        A v = __builtin_fma(wi * rho, __builtin_fma((A)0.5, __builtin_fma(B, B, C), B), wi * rhom1);
+        A v = fmaa(wi * rho, fmaa((A)0.5, fmaa(B, B, C), B), wi * rhom1);
         if (fl & F_SOLID) v = (A)0;
         const T code = Codec<F>::template store<A>(v, tab);
         d0[(size_t)i * L.plane + n] = code;
