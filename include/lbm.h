@@ -115,7 +115,11 @@ typedef struct {
     int32_t block;           /* threads per workgroup: 64, 128, 256, 512 */
     int32_t cells_per_lane;  /* consecutive x cells per thread: 1, 2 (not FP64
                                 storage) or 4 (16-bit storage); every nx must
-                                be a multiple of it */
+                                be a multiple of it.  With staged = 1: cells
+                                per thread, 1 or 2 */
+    int32_t staged;          /* 1: LDS-staged kernel (row segments moved with
+                                16-byte accesses); every nx must be a multiple
+                                of 16 / bytes per DDF */
     int32_t persistent;      /* batched only: workgroups per CU of a persistent
                                 grid walking the tile table; 0 = one workgroup
                                 per tile */

@@ -57,8 +57,8 @@ class LbmDiag(ctypes.Structure):
 
 class LbmLaunch(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("cells_per_lane", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32)]
+                ("cells_per_lane", ctypes.c_int32), ("staged", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -309,10 +309,11 @@ class Lattices:
     def diagnostics(self, k: int = 0, u_ref=None) -> dict:
         return lbm_diagnostics(self.h, k, u_ref).as_dict()
 
-    def set_launch(self, mode=None, block=None, cells_per_lane=None, persistent=None, graph_steps=None):
+    def set_launch(self, mode=None, block=None, cells_per_lane=None, staged=None, persistent=None,
+                   graph_steps=None):
         c = lbm_get_launch(self.h)
         for name, v in (("mode", mode), ("block", block), ("cells_per_lane", cells_per_lane),
-                        ("persistent", persistent), ("graph_steps", graph_steps)):
+                        ("staged", staged), ("persistent", persistent), ("graph_steps", graph_steps)):
             if v is not None:
                 setattr(c, name, int(v))
         lbm_set_launch(self.h, c)

@@ -27,6 +27,7 @@ struct LatDev {
     double wall_u[3];        // velocity of MOVING walls
     double eq_rho;           // state of EQ cells
     double eq_u[3];
+    const void* eq_codes;    // q stored codes of the EQ cells' equilibrium
     int32_t forced;          // any force component != 0
     int32_t pad;
 };
@@ -46,6 +47,7 @@ struct EncEntry {
 struct StepLaunch {
     int q, storage, arith, collision;
     int block, cpl;
+    int staged;              // LDS-staged kernel (cpl = cells per thread)
     int parity;
     const LatDev* lats;      // batched: device array of descriptors
     const Tile* tiles;       // batched: device array of tiles
@@ -62,6 +64,9 @@ hipError_t launch_init(int q, int storage, int arith, const LatDev& lat, const d
                        const double* u, const EncEntry* enc, hipStream_t st);
 hipError_t launch_moments(int q, int storage, int arith, const LatDev& lat, int parity,
                           double* rho, double* u, hipStream_t st);
+hipError_t launch_eq_codes(int q, int storage, int arith, const LatDev& lat, void* out,
+                           const EncEntry* enc, hipStream_t st);
+size_t staged_lds_bytes(int q, int storage, int block, int cpl);
 
 // Per-format launch hooks, defined in kern_<format>.hip.
 #define LBM_DECLARE_FORMAT(NAME)                                                              \
@@ -71,6 +76,8 @@ hipError_t launch_moments(int q, int storage, int arith, const LatDev& lat, int 
                            const double* u, const EncEntry* enc, hipStream_t st);            \
     hipError_t moments_##NAME(int q, int arith, const LatDev& lat, int parity, double* rho,  \
                               double* u, hipStream_t st);                                    \
+    hipError_t eq_codes_##NAME(int q, int arith, const LatDev& lat, void* out,               \
+                               const EncEntry* enc, hipStream_t st);                         \
     hipError_t diag_##NAME(int q, int arith, const LatDev& lat, int parity,                  \
                            const double* u_ref, double* partials, int nblocks, hipStream_t st);
 LBM_DECLARE_FORMAT(fp64)

@@ -557,6 +557,152 @@ __device__ __forceinline__ const EncEntry* stage_table(const EncEntry* g, EncEnt
 }
 
 // One lattice: workgroup b handles segment b % segs of row b / segs.
+// ------------------------------------------------------------ LDS-staged step
+// A workgroup of B threads owns a row segment of S = B*K cells.  Its waves
+// load, for every direction i, the segment of the source row (y - c_iy,
+// z - c_iz) with 16-byte accesses into LDS, plus the one element the x-shift
+// needs beyond the segment (periodic wrap), and the segment's flag bytes.
+// Each thread then pulls the DDFs of its K cells from LDS (the x-shift is an
+// LDS offset), collides, and -- after a barrier -- writes the new codes back
+// in place; the waves finally store every direction's segment of the own row
+// with 16-byte accesses.  Wall cells are written as zero and EQ cells with
+// the lattice's equilibrium codes, which is what both buffers hold there.
+// Requires nx to be a multiple of the elements per 16 bytes.
+template <class T> constexpr int kVecElems = 16 / (int)sizeof(T);
+
+template <int Q, class T>
+__host__ __device__ constexpr size_t staged_lds(int block, int cpl) {
+    return (size_t)Q * ((size_t)block * cpl + 2 * kVecElems<T>) * sizeof(T) + (size_t)block * cpl;
+}
+
+template <int Q, int F, class A, int COLL, int K>
+__device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z, int parity,
+                                            const EncEntry* tab, char* lds) {
+    using T = typename Codec<F>::T;
+    constexpr int VE = kVecElems<T>;
+    constexpr int OFF = VE;
+    const uint32_t B = blockDim.x;
+    const uint32_t S = B * K;
+    const uint32_t RS = S + 2 * OFF;                       // LDS row stride (elements)
+    T* s_ddf = (T*)lds;
+    uint8_t* s_fl = (uint8_t*)(s_ddf + (size_t)Q * RS);
+    const uint32_t nx = L.nx, ny = L.ny, nz = L.nz;
+    const uint32_t seg = min(S, nx - x0);                  // multiple of VE
+    const uint32_t nvec = seg / VE;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = B >> 6;
+    const T* __restrict__ src = (const T*)L.f[parity];
+    T* __restrict__ dst = (T*)L.f[parity ^ 1];
+    const size_t plane = L.plane;
+    const uint32_t row = (y + z * ny) * nx;
+
+    // ---- load the source row segments
+    for (uint32_t i = wave; i < (uint32_t)Q; i += nwaves) {
+        const int cx = VelSetTables::c[i][0], cy = VelSetTables::c[i][1], cz = VelSetTables::c[i][2];
+        const uint32_t sy = wrap_add(y, -cy, ny), sz = wrap_add(z, -cz, nz);
+        const T* rp = src + (size_t)i * plane + (sy + sz * ny) * nx + x0;
+        T* lp = s_ddf + i * RS + OFF;
+        for (uint32_t k = lane; k < nvec; k += 64)
+            *(uint4*)(lp + k * VE) = *(const uint4*)(rp + k * VE);
+        if (lane == 0 && cx != 0) {
+            const T* r0 = rp - x0;
+            if (cx > 0) lp[-1] = r0[x0 == 0 ? nx - 1 : x0 - 1];
+            else lp[seg] = r0[x0 + seg == nx ? 0 : x0 + seg];
+        }
+    }
+    for (uint32_t k = threadIdx.x; k < seg / 2; k += B)
+        ((uint16_t*)s_fl)[k] = ((const uint16_t*)(L.flags + row + x0))[k];
+    __syncthreads();
+
+    // ---- collide the K cells of this thread
+    T codes[K][Q];
+    const T* eqc = (const T*)L.eq_codes;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const uint32_t xl = threadIdx.x + k * B;
+        if (xl >= seg) continue;
+        const uint8_t fl = s_fl[xl];
+        if (fl & F_SOLID) {
+#pragma unroll
+            for (int i = 0; i < Q; i++) codes[k][i] = Codec<F>::template store<A>((A)0, tab);
+        } else if (fl & F_EQ) {
+#pragma unroll
+            for (int i = 0; i < Q; i++) codes[k][i] = eqc[i];
+        } else {
+            A f[Q], fo[Q];
+#pragma unroll
+            for (int i = 0; i < Q; i++)
+                f[i] = Codec<F>::template load<A>(s_ddf[i * RS + OFF + xl - VelSet<Q>::c[i][0]]);
+            const bool near = (fl & F_NEAR) != 0;
+            if (__any(near)) {
+                const uint32_t x = x0 + xl;
+                const uint32_t xm = x == 0 ? nx - 1 : x - 1;
+                const uint32_t xp = x + 1 == nx ? 0 : x + 1;
+                RowCtx rc;
+                make_rows(L, y, z, rc);
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
+                    if (near && (fs & F_SOLID)) {
+                        A v = Codec<F>::template load<A>(ld_off(src + (size_t)opp(i) * plane, row + x));
+                        if (fs & F_MOVING) {
+                            const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                             VelSet<Q>::c[i][2] * L.wall_u[2]);
+                            v += (A)(6.0 * VelSet<Q>::w(i)) * cu;
+                        }
+                        f[i] = v;
+                    }
+                }
+            }
+            collide<Q, COLL, A, (sizeof(T) >= 4)>(L, f, fo);
+#pragma unroll
+            for (int i = 0; i < Q; i++) codes[k][i] = Codec<F>::template store<A>(fo[i], tab);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const uint32_t xl = threadIdx.x + k * B;
+        if (xl < seg) {
+#pragma unroll
+            for (int i = 0; i < Q; i++) s_ddf[i * RS + OFF + xl] = codes[k][i];
+        }
+    }
+    __syncthreads();
+
+    // ---- store the own row segment of every direction
+    for (uint32_t i = wave; i < (uint32_t)Q; i += nwaves) {
+        T* rp = dst + (size_t)i * plane + row + x0;
+        const T* lp = s_ddf + i * RS + OFF;
+        for (uint32_t k = lane; k < nvec; k += 64)
+            *(uint4*)(rp + k * VE) = *(const uint4*)(lp + k * VE);
+    }
+    __syncthreads();                                        // LDS is reused by the next tile
+}
+
+template <int Q, int F, class A, int COLL, int K>
+__global__ void __launch_bounds__(512) k_step_staged_single(LatDev L, int parity, uint32_t segs,
+                                                            const EncEntry* __restrict__ enc) {
+    extern __shared__ __align__(16) char lds_dyn[];
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    const EncEntry* tab = stage_table<F>(enc, s_tab);
+    const uint32_t b = blockIdx.x;
+    const uint32_t seg = b % segs, row = b / segs;
+    staged_tile<Q, F, A, COLL, K>(L, seg * blockDim.x * K, row % L.ny, row / L.ny, parity, tab, lds_dyn);
+}
+
+template <int Q, int F, class A, int COLL, int K>
+__global__ void __launch_bounds__(512) k_step_staged_batched(const LatDev* __restrict__ lats,
+                                                             const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                             int parity, const EncEntry* __restrict__ enc) {
+    extern __shared__ __align__(16) char lds_dyn[];
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    const EncEntry* tab = stage_table<F>(enc, s_tab);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        staged_tile<Q, F, A, COLL, K>(lats[tl.lat], tl.x0, tl.y, tl.z, parity, tab, lds_dyn);
+    }
+}
+
 template <int Q, int F, class A, int COLL, int CPL>
 __device__ __forceinline__ void run_tile(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z, int parity,
                                          const EncEntry* tab) {
@@ -590,8 +736,31 @@ __global__ void __launch_bounds__(512) k_step_batched(const LatDev* __restrict__
 }
 
 // ------------------------------------------------------------ initialisation
+// Stored code of direction i of the (shifted) equilibrium of rho, u.
+template <int Q, int F, class A>
+__device__ __forceinline__ typename Codec<F>::T eq_code(int i, A rho, A ux, A uy, A uz, const EncEntry* tab) {
+    const A C = (A)(-3) * (ux * ux + uy * uy + uz * uz);
+    const A rhom1 = rho - (A)1;
+    const A wi = (A)VelSet<Q>::w(i);
+    const A B = (A)3 * cdot_i<Q, A>(i, ux, uy, uz);
+    return Codec<F>::template store<A>(fmaa(wi * rho, fmaa((A)0.5, fmaa(B, B, C), B), wi * rhom1), tab);
+}
+
+// The q codes of the lattice's EQ cells (eq_rho, eq_u), computed once; the
+// initialisation and the step write EQ cells from this table, so both agree
+// bit for bit.
+template <int Q, int F, class A>
+__global__ void __launch_bounds__(64) k_eq_codes(LatDev L, typename Codec<F>::T* __restrict__ out,
+                                                 const EncEntry* __restrict__ enc) {
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    const EncEntry* tab = stage_table<F>(enc, s_tab);
+    const int i = threadIdx.x;
+    if (i < Q) out[i] = eq_code<Q, F, A>(i, (A)L.eq_rho, (A)L.eq_u[0], (A)L.eq_u[1], (A)L.eq_u[2], tab);
+}
+
 // DDFs of the (shifted) equilibrium of rho, u (the paper's initialize kernel)
-// written to both buffers; wall cells get zeros, EQ cells eq_rho/eq_u.
+// written to both buffers; wall cells get zeros, EQ cells the lattice's
+// equilibrium codes.
 template <int Q, int F, class A>
 __global__ void __launch_bounds__(256) k_init(LatDev L, const double* __restrict__ rho_in,
                                               const double* __restrict__ u_in,
@@ -604,23 +773,16 @@ __global__ void __launch_bounds__(256) k_init(LatDev L, const double* __restrict
     if (n >= N) return;
     const uint8_t fl = L.flags[n];
     A rho = (A)1, ux = (A)0, uy = (A)0, uz = (A)0;
-    if (fl & F_EQ) {
-        rho = (A)L.eq_rho; ux = (A)L.eq_u[0]; uy = (A)L.eq_u[1]; uz = (A)L.eq_u[2];
-    } else {
-        if (rho_in) rho = (A)rho_in[n];
-        if (u_in) { ux = (A)u_in[n]; uy = (A)u_in[N + n]; uz = (A)u_in[2 * N + n]; }
-    }
-    const A C = (A)(-3) * (ux * ux + uy * uy + uz * uz);
-    const A rhom1 = rho - (A)1;
+    if (rho_in) rho = (A)rho_in[n];
+    if (u_in) { ux = (A)u_in[n]; uy = (A)u_in[N + n]; uz = (A)u_in[2 * N + n]; }
+    const T* eqc = (const T*)L.eq_codes;
     T* d0 = (T*)L.f[0];
     T* d1 = (T*)L.f[1];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        const A wi = (A)VelSet<Q>::w(i);
-        const A B = (A)3 * cdot_i<Q, A>(i, ux, uy, uz);
-        A v = fmaa(wi * rho, fmaa((A)0.5, fmaa(B, B, C), B), wi * rhom1);
-        if (fl & F_SOLID) v = (A)0;
-        const T code = Codec<F>::template store<A>(v, tab);
+        T code = eq_code<Q, F, A>(i, rho, ux, uy, uz, tab);
+        if (fl & F_EQ) code = eqc[i];
+        if (fl & F_SOLID) code = Codec<F>::template store<A>((A)0, tab);
         d0[(size_t)i * L.plane + n] = code;
         d1[(size_t)i * L.plane + n] = code;
     }
@@ -793,8 +955,32 @@ struct FormatLaunchers {
                            s.lats, s.tiles, s.ntiles, s.parity, s.enc);
         return hipGetLastError();
     }
+    template <int Q, class A, int COLL, int K>
+    static hipError_t staged_single_k(const StepLaunch& s, const LatDev& L) {
+        using T = typename Codec<F>::T;
+        const uint32_t per_wg = (uint32_t)s.block * K;
+        const uint32_t segs = (L.nx + per_wg - 1) / per_wg;
+        const uint32_t grid = segs * L.ny * L.nz;
+        const size_t lds = staged_lds<Q, T>(s.block, K);
+        hipLaunchKernelGGL((k_step_staged_single<Q, F, A, COLL, K>), dim3(grid), dim3(s.block), lds, s.stream, L,
+                           s.parity, segs, s.enc);
+        return hipGetLastError();
+    }
+    template <int Q, class A, int COLL, int K>
+    static hipError_t staged_batched_k(const StepLaunch& s) {
+        using T = typename Codec<F>::T;
+        const size_t lds = staged_lds<Q, T>(s.block, K);
+        hipLaunchKernelGGL((k_step_staged_batched<Q, F, A, COLL, K>), dim3(s.grid), dim3(s.block), lds, s.stream,
+                           s.lats, s.tiles, s.ntiles, s.parity, s.enc);
+        return hipGetLastError();
+    }
     template <int Q, class A, int COLL>
     static hipError_t single_qac(const StepLaunch& s, const LatDev& L) {
+        if (s.staged) {
+            if (s.cpl == 1) return staged_single_k<Q, A, COLL, 1>(s, L);
+            if (s.cpl == 2) return staged_single_k<Q, A, COLL, 2>(s, L);
+            return hipErrorInvalidValue;
+        }
         if (s.cpl == 1) return single_cpl<Q, A, COLL, 1>(s, L);
         if constexpr (kMaxCpl >= 2)
             if (s.cpl == 2) return single_cpl<Q, A, COLL, 2>(s, L);
@@ -804,6 +990,11 @@ struct FormatLaunchers {
     }
     template <int Q, class A, int COLL>
     static hipError_t batched_qac(const StepLaunch& s) {
+        if (s.staged) {
+            if (s.cpl == 1) return staged_batched_k<Q, A, COLL, 1>(s);
+            if (s.cpl == 2) return staged_batched_k<Q, A, COLL, 2>(s);
+            return hipErrorInvalidValue;
+        }
         if (s.cpl == 1) return batched_cpl<Q, A, COLL, 1>(s);
         if constexpr (kMaxCpl >= 2)
             if (s.cpl == 2) return batched_cpl<Q, A, COLL, 2>(s);

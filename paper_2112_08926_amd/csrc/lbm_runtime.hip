@@ -113,6 +113,17 @@ hipError_t launch_moments(int q, int storage, int arith, const LatDev& lat, int 
     LBM_FORMAT_SWITCH(storage, E)
 #undef E
 }
+hipError_t launch_eq_codes(int q, int storage, int arith, const LatDev& lat, void* out, const EncEntry* enc,
+                           hipStream_t st) {
+#define E(N) eq_codes_##N(q, arith, lat, out, enc, st)
+    LBM_FORMAT_SWITCH(storage, E)
+#undef E
+}
+size_t staged_lds_bytes(int q, int storage, int block, int cpl) {
+    const int b = storage == S_FP64 ? 8 : (storage == S_FP32 ? 4 : 2);
+    const size_t ve = 16 / b;
+    return (size_t)q * ((size_t)block * cpl + 2 * ve) * b + (size_t)block * cpl;
+}
 }  // namespace lbm
 
 // ------------------------------------------------------------------ small kernels
@@ -191,6 +202,7 @@ struct Lattice {
     uint32_t plane = 0;
     void* f[2] = {nullptr, nullptr};
     uint8_t* flags = nullptr;
+    void* eq_codes = nullptr;   // q codes of the EQ state
     LatDev dev{};
 };
 
@@ -248,6 +260,7 @@ static void fill_dev(Lattice& L, int arith) {
     d.f[0] = L.f[0];
     d.f[1] = L.f[1];
     d.flags = L.flags;
+    d.eq_codes = L.eq_codes;
     d.nx = (uint32_t)L.p.nx;
     d.ny = (uint32_t)L.p.ny;
     d.nz = (uint32_t)L.p.nz;
@@ -321,7 +334,7 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
         return fail(LBM_EDEVICE, "no HIP device");
     }
     h->num_cus = prop.multiProcessorCount;
-    h->launch = {n_lattices > 1 ? LBM_LAUNCH_BATCHED : LBM_LAUNCH_PER_LATTICE, 256, 1, 0, 0};
+    h->launch = {n_lattices > 1 ? LBM_LAUNCH_BATCHED : LBM_LAUNCH_PER_LATTICE, 256, 1, 0, 0, 0};
     lbm_status st = device_table(h->storage, &h->enc);
     if (st != LBM_OK) { delete h; return st; }
     const int b = ddf_bytes(h->storage);
@@ -335,7 +348,8 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
         L.f[0] = dev_alloc(h, bytes);
         L.f[1] = dev_alloc(h, bytes);
         L.flags = (uint8_t*)dev_alloc(h, L.N);
-        if (!L.f[0] || !L.f[1] || !L.flags) {
+        L.eq_codes = dev_alloc(h, 27 * 8);
+        if (!L.f[0] || !L.f[1] || !L.flags || !L.eq_codes) {
             lbm_destroy(h);
             return fail(LBM_ENOMEM, "device allocation of lattice %d (%zu bytes per buffer) failed", k, bytes);
         }
@@ -346,6 +360,10 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
             return fail(LBM_EDEVICE, "hipMemsetAsync failed");
         }
         fill_dev(L, h->arith);
+        if (launch_eq_codes(h->q, h->storage, h->arith, L.dev, L.eq_codes, h->enc, h->stream) != hipSuccess) {
+            lbm_destroy(h);
+            return fail(LBM_EDEVICE, "equilibrium code table failed");
+        }
         st = run_init(h, L, nullptr, nullptr);
         if (st != LBM_OK) { lbm_destroy(h); return st; }
     }
@@ -378,6 +396,7 @@ extern "C" void lbm_destroy(lbm_handle* h) {
         dev_free(h, L.f[0]);
         dev_free(h, L.f[1]);
         dev_free(h, L.flags);
+        dev_free(h, L.eq_codes);
     }
     dev_free(h, h->d_partials);
     dev_free(h, h->d_out);
@@ -426,6 +445,7 @@ static StepLaunch make_launch(lbm_handle* h, const lbm_launch& cfg, int parity) 
     s.collision = h->collision;
     s.block = cfg.block;
     s.cpl = cfg.cells_per_lane;
+    s.staged = cfg.staged;
     s.parity = parity;
     s.lats = h->d_lats;
     s.tiles = h->d_tiles;
@@ -656,6 +676,24 @@ extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_
 static lbm_status check_launch(lbm_handle* h, const lbm_launch& c) {
     if (c.mode != LBM_LAUNCH_PER_LATTICE && c.mode != LBM_LAUNCH_BATCHED) return fail(LBM_EINVAL, "unknown launch mode");
     if (c.block != 64 && c.block != 128 && c.block != 256 && c.block != 512) return fail(LBM_EINVAL, "block must be 64..512");
+    if (c.staged != 0 && c.staged != 1) return fail(LBM_EINVAL, "staged must be 0 or 1");
+    if (c.staged) {
+        if (c.cells_per_lane != 1 && c.cells_per_lane != 2)
+            return fail(LBM_EINVAL, "the staged kernel takes 1 or 2 cells per thread");
+        if (staged_lds_bytes(h->q, h->storage, c.block, c.cells_per_lane) > 65536)
+            return fail(LBM_EUNSUPPORTED, "staged tile of %d cells does not fit 64 KiB of LDS",
+                        c.block * c.cells_per_lane);
+        const int ve = 16 / ddf_bytes(h->storage);
+        for (size_t k = 0; k < h->lats.size(); k++)
+            if (h->lats[k].p.nx % ve)
+                return fail(LBM_EINVAL, "lattice %zu: the staged kernel needs nx to be a multiple of %d", k, ve);
+        if (c.graph_steps < 0 || (c.graph_steps & 1) || c.graph_steps > 100000)
+            return fail(LBM_EINVAL, "graph_steps must be even and >= 0");
+        if (c.graph_steps > 0 && h->stream == nullptr)
+            return fail(LBM_EINVAL, "HIP graphs need a non-null stream (the null stream cannot be captured)");
+        if (c.persistent < 0 || c.persistent > 64) return fail(LBM_EINVAL, "persistent must be in [0, 64]");
+        return LBM_OK;
+    }
     if (c.cells_per_lane != 1 && c.cells_per_lane != 2 && c.cells_per_lane != 4)
         return fail(LBM_EINVAL, "cells_per_lane must be 1, 2 or 4");
     if (c.cells_per_lane == 4 && ddf_bytes(h->storage) != 2)
@@ -695,14 +733,17 @@ extern "C" lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launc
     const lbm_launch keep = h->launch;
     std::vector<lbm_launch> cands;
     const int blocks[] = {64, 128, 256, 512};
-    for (int cpl : {1, 2, 4}) {
-        for (int b : blocks) {
-            const lbm_launch c{LBM_LAUNCH_PER_LATTICE, b, cpl, 0, keep.graph_steps};
-            if (check_launch(h, c) != LBM_OK) continue;
-            cands.push_back(c);
-            if (h->lats.size() > 1) {
-                cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, 0, keep.graph_steps});
-                for (int pers : {2, 4, 8}) cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, pers, keep.graph_steps});
+    for (int staged : {0, 1}) {
+        for (int cpl : {1, 2, 4}) {
+            for (int b : blocks) {
+                const lbm_launch c{LBM_LAUNCH_PER_LATTICE, b, cpl, staged, 0, keep.graph_steps};
+                if (check_launch(h, c) != LBM_OK) continue;
+                cands.push_back(c);
+                if (h->lats.size() > 1) {
+                    cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, staged, 0, keep.graph_steps});
+                    for (int pers : {2, 4, 8})
+                        cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, staged, pers, keep.graph_steps});
+                }
             }
         }
     }
