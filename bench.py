@@ -94,7 +94,7 @@ def measure_format(storage, n, steps, warmup):
             "mlups_fluid": n_fluid / (ms * 1e-3) / 1e6, "alg_bytes_per_launch": alg_bytes,
             "achieved_GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
             "kinetic_energy": d["kinetic_energy"], "nonfinite": d["nonfinite_cells"],
-            "launch": {"block": cfg["block"], "cells_per_lane": cfg["cells_per_lane"]}}
+            "launch": {k: cfg[k] for k in ("block", "cells_per_lane", "staged")}}
 
 
 def copy_bandwidth(nbytes=4 << 30, reps=10):

@@ -129,11 +129,11 @@ template <> struct Codec<S_FP16S> {
     using T = uint16_t;
     static constexpr bool kTable = false;
     template <class A> __device__ __forceinline__ static A load(T v) { return half_decode(v) * 0x1p-15f; }
-    // The sign bit is copied explicitly: the compiler fuses the scale and the
-    // conversion into one multiply-add with a +0 addend, which would turn -0
-    // into +0.
+    // The 2^15 scale is an exponent add (ldexp: exact, keeps -0); a plain
+    // multiply gets fused with the conversion into a multiply-add with a +0
+    // addend, which would turn -0 into +0.
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) {
-        return (T)(half_encode(v * 32768.0f) | ((f2u(v) >> 16) & 0x8000u));
+        return half_encode(__builtin_ldexpf(v, 15));
     }
 };
 template <> struct Codec<S_FP16C> {

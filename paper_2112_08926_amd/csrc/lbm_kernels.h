@@ -123,9 +123,11 @@ template <class T>
 __device__ __forceinline__ T ld_off(const T* base, uint32_t idx) {
     return *(const T*)((const char*)base + (uint32_t)(idx * (uint32_t)sizeof(T)));
 }
+// New DDFs are streamed out: nontemporal stores (each element is written
+// once per step and read back only by the next step).
 template <class T>
 __device__ __forceinline__ void st_off(T* base, uint32_t idx, T v) {
-    *(T*)((char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))) = v;
+    __builtin_nontemporal_store(v, (T*)((char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))));
 }
 
 template <int Q, int F, class A>

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbm.h"
+#include "lbm.h"
 #include "lbm_codecs.h"
 #include "lbm_internal.h"
 #include "lbm_kernels.h"

@@ -170,8 +170,11 @@ def test_diagnostics_match_reference(lbm, orc):
         d = g.diagnostics(0, u_ref)
     for k in ("mass", "kinetic_energy", "u_max", "l2_error"):
         assert d[k] == pytest.approx(dr[k], rel=1e-11), k
-    assert np.allclose(d["momentum"], dr["momentum"], rtol=1e-11, atol=1e-18)
-    assert np.allclose(d["force_on_solid"], dr["force_on_solid"], rtol=1e-10, atol=1e-16)
+    # components that vanish by symmetry are rounding noise on both sides
+    scale = np.abs(dr["momentum"]).max()
+    assert np.allclose(d["momentum"], dr["momentum"], rtol=1e-11, atol=1e-12 * scale)
+    fscale = np.abs(dr["force_on_solid"]).max()
+    assert np.allclose(d["force_on_solid"], dr["force_on_solid"], rtol=1e-10, atol=1e-11 * fscale)
     assert d["nonfinite_cells"] == 0
 
 
