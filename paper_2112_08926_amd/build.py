@@ -23,6 +23,9 @@ ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    # FMAs only where the source writes them: every kernel variant then rounds
+    # identically (the default contraction fuses differently per context)
+    "-ffp-contract=off",
     "-Wno-unused-result", "-Wno-unused-function",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
