@@ -105,28 +105,46 @@ __host__ __device__ __forceinline__ float decode16(int fmt, uint32_t c) {
 // ---------------------------------------------------------------- storage traits
 // Codec<F>::T is the stored type; load() returns the arithmetic value, store()
 // takes it.  `tab` is the encoder table in LDS (used by FP16C and posits).
+// load_raw()/store_raw() work in units of 2^-kRawExp: the step kernel does
+// its arithmetic in those units (every constant scaled by 2^kRawExp; scaling
+// by a power of two is exact, so the result is the same), which removes the
+// FP16S range shift from every load and store.
 template <int F> struct Codec;
 
-template <> struct Codec<S_FP64> {
+template <int F>
+struct RawCodec {
+    template <class A, class TT> __device__ __forceinline__ static A load_raw(TT v) {
+        return Codec<F>::template load<A>(v);
+    }
+    template <class A> __device__ __forceinline__ static auto store_raw(A v, const EncEntry* t) {
+        return Codec<F>::template store<A>(v, t);
+    }
+};
+
+template <> struct Codec<S_FP64> : RawCodec<S_FP64> {
     using T = double;
+    static constexpr int kRawExp = 0;
     static constexpr bool kTable = false;
     template <class A> __device__ __forceinline__ static A load(T v) { return (A)v; }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return (T)v; }
 };
-template <> struct Codec<S_FP32> {
+template <> struct Codec<S_FP32> : RawCodec<S_FP32> {
     using T = float;
+    static constexpr int kRawExp = 0;
     static constexpr bool kTable = false;
     template <class A> __device__ __forceinline__ static A load(T v) { return (A)v; }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return (T)v; }
 };
-template <> struct Codec<S_FP16> {
+template <> struct Codec<S_FP16> : RawCodec<S_FP16> {
     using T = uint16_t;
+    static constexpr int kRawExp = 0;
     static constexpr bool kTable = false;
     template <class A> __device__ __forceinline__ static A load(T v) { return half_decode(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return half_encode(v); }
 };
 template <> struct Codec<S_FP16S> {
     using T = uint16_t;
+    static constexpr int kRawExp = 15;          // the stored FP16 value is x * 2^15
     static constexpr bool kTable = false;
     template <class A> __device__ __forceinline__ static A load(T v) { return half_decode(v) * 0x1p-15f; }
     // The 2^15 scale is an exponent add (ldexp: exact, keeps -0); a plain
@@ -135,27 +153,33 @@ template <> struct Codec<S_FP16S> {
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) {
         return half_encode(__builtin_ldexpf(v, 15));
     }
+    template <class A> __device__ __forceinline__ static A load_raw(T v) { return half_decode(v); }
+    template <class A> __device__ __forceinline__ static T store_raw(A v, const EncEntry*) { return half_encode(v); }
 };
-template <> struct Codec<S_FP16C> {
+template <> struct Codec<S_FP16C> : RawCodec<S_FP16C> {
     using T = uint16_t;
+    static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return fp16c_decode(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
 };
-template <> struct Codec<S_P16_0S> {
+template <> struct Codec<S_P16_0S> : RawCodec<S_P16_0S> {
     using T = uint16_t;
+    static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode<0>(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
 };
-template <> struct Codec<S_P16_1S> {
+template <> struct Codec<S_P16_1S> : RawCodec<S_P16_1S> {
     using T = uint16_t;
+    static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode<1>(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
 };
-template <> struct Codec<S_P16_2C> {
+template <> struct Codec<S_P16_2C> : RawCodec<S_P16_2C> {
     using T = uint16_t;
+    static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return p162c_decode(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }

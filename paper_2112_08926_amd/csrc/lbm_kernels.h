@@ -130,7 +130,17 @@ __device__ __forceinline__ void st_off(T* base, uint32_t idx, T v) {
     __builtin_nontemporal_store(v, (T*)((char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))));
 }
 
-template <int Q, int F, class A>
+// RAW: values in the storage's raw units (2^-kRawExp), as the step uses them;
+// otherwise physical values (moments and diagnostics).
+template <int Q, int F, class A, bool RAW>
+__device__ __forceinline__ A load_ddf(typename Codec<F>::T v) {
+    if constexpr (RAW) return Codec<F>::template load_raw<A>(v);
+    else return Codec<F>::template load<A>(v);
+}
+template <int F, bool RAW>
+constexpr double raw_scale() { return RAW ? (double)(1u << Codec<F>::kRawExp) : 1.0; }
+
+template <int Q, int F, class A, bool RAW>
 __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
                                      const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp,
                                      uint32_t n, bool near, A (&f)[Q]) {
@@ -139,7 +149,7 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
-        f[i] = Codec<F>::template load<A>(ld_off(p, src_x<Q>(i, x, xm, xp)));
+        f[i] = load_ddf<Q, F, A, RAW>(ld_off(p, src_x<Q>(i, x, xm, xp)));
     }
     if (__any(near)) {
         // A wall source hands back what this cell sent towards it last step.
@@ -147,11 +157,11 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
         for (int i = 1; i < Q; i++) {
             const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
             if (near && (fs & F_SOLID)) {
-                A v = Codec<F>::template load<A>(ld_off(src + (size_t)opp(i) * plane, n));
+                A v = load_ddf<Q, F, A, RAW>(ld_off(src + (size_t)opp(i) * plane, n));
                 if (fs & F_MOVING) {
                     const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                      VelSet<Q>::c[i][2] * L.wall_u[2]);
-                    v += (A)(6.0 * VelSet<Q>::w(i)) * cu;
+                    v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, RAW>()) * cu;
                 }
                 f[i] = v;
             }
@@ -160,12 +170,9 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
 }
 
 // ------------------------------------------------------------ fields
+// Momentum by alternating pair sums (Sec. 2.2), in index order.
 template <int Q, class A>
-__device__ __forceinline__ void fields(const A (&f)[Q], A& rho, A (&j)[3]) {
-    A r = f[0];
-#pragma unroll
-    for (int i = 1; i < Q; i++) r += f[i];
-    rho = r + (A)1;
+__device__ __forceinline__ void fields_j(const A (&f)[Q], A (&j)[3]) {
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         A s = (A)0;
@@ -179,6 +186,24 @@ __device__ __forceinline__ void fields(const A (&f)[Q], A& rho, A (&j)[3]) {
     }
 }
 
+// Sum of the DDFs, f_0 first then in index order.
+template <int Q, class A>
+__device__ __forceinline__ A fields_sum(const A (&f)[Q]) {
+    A r = f[0];
+#pragma unroll
+    for (int i = 1; i < Q; i++) r += f[i];
+    return r;
+}
+
+template <int Q, class A>
+__device__ __forceinline__ void fields(const A (&f)[Q], A& rho, A (&j)[3]) {
+    A r = f[0];
+#pragma unroll
+    for (int i = 1; i < Q; i++) r += f[i];
+    rho = r + (A)1;                                          // the 1 of the shift last
+    fields_j<Q, A>(f, j);
+}
+
 // ------------------------------------------------------------ collision
 // Fused multiply-add in the arithmetic precision (__builtin_fma alone would
 // promote float operands to double).
@@ -188,24 +213,35 @@ template <class A> __device__ __forceinline__ A fmaa(A a, A b, A c) {
 }
 
 // Computes the post-collision DDFs fo[] of one cell from the pulled f[].
+// f and fo are in units of 2^-E (E = the storage's raw exponent, see
+// Codec::load_raw): density is sum(f) 2^-E + 1 and every term that enters
+// fo is multiplied by 2^E; being powers of two these scalings are exact.
 // Opposite directions i, i+1 share B (with opposite sign) and B^2 + C.
 // SRT evaluates each f^eq in the paper's three-FMA order and collides with
 // one FMA.  TRT needs only the pair sums and differences of f^eq, which
 // have the closed forms  feq_i + feq_j = w rho (B^2 + C) + 2 w (rho - 1)
 // and  feq_i - feq_j = 2 w rho B.
 // EXACT_DIV: u = j / rho as the paper's listing divides (FP32/FP64 storage,
-// where the division's rounding is visible); otherwise j * (1/rho), whose
-// extra rounding (1e-7 relative) is far below a 16-bit storage step.
-template <int Q, int COLL, class A, bool EXACT_DIV>
+// where the division's rounding is visible); otherwise j * (1/rho) with the
+// hardware reciprocal, whose error (~1e-7 relative) is far below a 16-bit
+// storage step.
+template <int Q, int COLL, class A, bool EXACT_DIV, int E>
 __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo)[Q]) {
-    A rho, j[3];
-    fields<Q, A>(f, rho, j);
+    static_assert(!EXACT_DIV || E == 0, "scaled units only with the reciprocal path");
+    constexpr double kSc = (double)(1u << E);
+    const A sc = (A)kSc;
+    A j[3];
+    const A r = fields_sum<Q, A>(f);                         // raw units
+    fields_j<Q, A>(f, j);
+    A rho;                                                   // the 1 of the shift added last
+    if constexpr (E == 0) rho = r + (A)1;
+    else rho = fmaa(r, (A)(1.0 / kSc), (A)1);
     const bool forced = L.forced != 0;
     const A Fx = (A)L.force[0], Fy = (A)L.force[1], Fz = (A)L.force[2];
     if (forced) {
-        j[0] += (A)0.5 * Fx;
-        j[1] += (A)0.5 * Fy;
-        j[2] += (A)0.5 * Fz;
+        j[0] += (A)(0.5 * kSc) * Fx;
+        j[1] += (A)(0.5 * kSc) * Fy;
+        j[2] += (A)(0.5 * kSc) * Fz;
     }
     A ux, uy, uz;
     if constexpr (EXACT_DIV) {
@@ -213,27 +249,29 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
         uy = clamp_c(j[1] / rho);
         uz = clamp_c(j[2] / rho);
     } else {
-        const A inv = (A)1 / rho;
+        A inv;
+        if constexpr (sizeof(A) == 4) inv = (A)(1.0 / kSc) * __builtin_amdgcn_rcpf(rho);
+        else inv = (A)(1.0 / kSc) / rho;
         ux = clamp_c(j[0] * inv);
         uy = clamp_c(j[1] * inv);
         uz = clamp_c(j[2] * inv);
     }
-    const A C = (A)(-3) * (ux * ux + uy * uy + uz * uz);
+    const A C = (A)(-3) * fmaa(ux, ux, fmaa(uy, uy, uz * uz));
     const A rhom1 = rho - (A)1;
     const A u3x = (A)3 * ux, u3y = (A)3 * uy, u3z = (A)3 * uz;
     const A w = (A)L.omega, wm = (A)L.omega_m;
-    const A uF = ux * Fx + uy * Fy + uz * Fz;
-    const A w0 = (A)VelSet<Q>::w(0);
+    const A uF = fmaa(ux, Fx, fmaa(uy, Fy, uz * Fz));
+    const A w0 = (A)(VelSet<Q>::w(0) * kSc);
     const A feq0 = fmaa(w0 * rho, (A)0.5 * C, w0 * rhom1);
 
     if (COLL == 0) {
         const A omw = (A)1 - w;
-        const A pre = (A)1 - (A)0.5 * w;
+        const A pre = ((A)1 - (A)0.5 * w) * sc;
         fo[0] = fmaa(omw, f[0], w * feq0);
-        if (forced) fo[0] += pre * (w0 * ((A)(-3) * uF));
+        if (forced) fo[0] += pre * ((A)VelSet<Q>::w(0) * ((A)(-3) * uF));
 #pragma unroll
         for (int i = 1; i < Q; i += 2) {
-            const A wi = (A)VelSet<Q>::w(i);
+            const A wi = (A)(VelSet<Q>::w(i) * kSc);
             const A B = cdot_i<Q, A>(i, u3x, u3y, u3z);
             const A t = fmaa(B, B, C);
             const A ei = fmaa(wi * rho, fmaa((A)0.5, t, B), wi * rhom1);
@@ -241,22 +279,23 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
             fo[i] = fmaa(omw, f[i], w * ei);
             fo[i + 1] = fmaa(omw, f[i + 1], w * ej);
             if (forced) {
+                const A wp = (A)VelSet<Q>::w(i);
                 const A cF = cdot_i<Q, A>(i, Fx, Fy, Fz);
                 const A cu = cdot_i<Q, A>(i, ux, uy, uz);
-                const A sym = wi * ((A)9 * cu * cF - (A)3 * uF);
-                const A anti = wi * (A)3 * cF;
+                const A sym = wp * ((A)9 * cu * cF - (A)3 * uF);
+                const A anti = wp * (A)3 * cF;
                 fo[i] += pre * (sym + anti);
                 fo[i + 1] += pre * (sym - anti);
             }
         }
     } else {
         const A hw = (A)0.5 * w, hwm = (A)0.5 * wm;
-        const A prep = (A)1 - hw, prem = (A)1 - hwm;
+        const A prep = ((A)1 - hw) * sc, prem = ((A)1 - hwm) * sc;
         fo[0] = fmaa(-w, f[0] - feq0, f[0]);
-        if (forced) fo[0] += prep * (w0 * ((A)(-3) * uF));
+        if (forced) fo[0] += prep * ((A)VelSet<Q>::w(0) * ((A)(-3) * uF));
 #pragma unroll
         for (int i = 1; i < Q; i += 2) {
-            const A wi = (A)VelSet<Q>::w(i);
+            const A wi = (A)(VelSet<Q>::w(i) * kSc);
             const A B = cdot_i<Q, A>(i, u3x, u3y, u3z);
             const A wr = wi * rho;
             const A esum = fmaa(wr, fmaa(B, B, C), (A)2 * wi * rhom1);
@@ -266,10 +305,11 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
             fo[i] = fmaa(-hw, s, fmaa(-hwm, d, f[i]));
             fo[i + 1] = fmaa(-hw, s, fmaa(hwm, d, f[i + 1]));
             if (forced) {
+                const A wp = (A)VelSet<Q>::w(i);
                 const A cF = cdot_i<Q, A>(i, Fx, Fy, Fz);
                 const A cu = cdot_i<Q, A>(i, ux, uy, uz);
-                const A sym = wi * ((A)9 * cu * cF - (A)3 * uF);
-                const A anti = wi * (A)3 * cF;
+                const A sym = wp * ((A)9 * cu * cF - (A)3 * uF);
+                const A anti = wp * (A)3 * cF;
                 fo[i] += prep * sym + prem * anti;
                 fo[i + 1] += prep * sym - prem * anti;
             }
@@ -295,13 +335,13 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     T* __restrict__ dst = (T*)L.f[parity ^ 1];
 
     A f[Q], fo[Q];
-    pull<Q, F, A>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
-    collide<Q, COLL, A, (sizeof(T) >= 4)>(L, f, fo);
+    pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+    collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
     const size_t plane = L.plane;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         T* p = dst + ((size_t)i * plane + rc.rows[4]);
-        st_off(p, x, Codec<F>::template store<A>(fo[i], tab));
+        st_off(p, x, Codec<F>::template store_raw<A>(fo[i], tab));
     }
 }
 
@@ -509,7 +549,7 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
     for (int k = 0; k < CPL; k++) {
         A f[Q], fo[Q];
 #pragma unroll
-        for (int i = 0; i < Q; i++) f[i] = Codec<F>::template load<A>(velem<T, CPL>(raw[i], k));
+        for (int i = 0; i < Q; i++) f[i] = load_ddf<Q, F, A, true>(velem<T, CPL>(raw[i], k));
         if (__any(near[k])) {
             const uint32_t xk = x + k;
             const uint32_t xkm = xk == 0 ? nx - 1 : xk - 1;
@@ -518,19 +558,19 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
             for (int i = 1; i < Q; i++) {
                 const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, xk, xkm, xkp)];
                 if (near[k] && (fs & F_SOLID)) {
-                    A v = Codec<F>::template load<A>(src[(size_t)opp(i) * plane + row + xk]);
+                    A v = load_ddf<Q, F, A, true>(src[(size_t)opp(i) * plane + row + xk]);
                     if (fs & F_MOVING) {
                         const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                          VelSet<Q>::c[i][2] * L.wall_u[2]);
-                        v += (A)(6.0 * VelSet<Q>::w(i)) * cu;
+                        v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, true>()) * cu;
                     }
                     f[i] = v;
                 }
             }
         }
-        collide<Q, COLL, A, (sizeof(T) >= 4)>(L, f, fo);
+        collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
 #pragma unroll
-        for (int i = 0; i < Q; i++) vset<T, CPL>(out[i], k, Codec<F>::template store<A>(fo[i], tab));
+        for (int i = 0; i < Q; i++) vset<T, CPL>(out[i], k, Codec<F>::template store_raw<A>(fo[i], tab));
     }
     if (__any(any_special)) {
         // wall and equilibrium cells keep their DDFs: element-wise stores
@@ -633,7 +673,7 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
             A f[Q], fo[Q];
 #pragma unroll
             for (int i = 0; i < Q; i++)
-                f[i] = Codec<F>::template load<A>(s_ddf[i * RS + OFF + xl - VelSet<Q>::c[i][0]]);
+                f[i] = load_ddf<Q, F, A, true>(s_ddf[i * RS + OFF + xl - VelSet<Q>::c[i][0]]);
             const bool near = (fl & F_NEAR) != 0;
             if (__any(near)) {
                 const uint32_t x = x0 + xl;
@@ -645,19 +685,19 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
                 for (int i = 1; i < Q; i++) {
                     const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
                     if (near && (fs & F_SOLID)) {
-                        A v = Codec<F>::template load<A>(ld_off(src + (size_t)opp(i) * plane, row + x));
+                        A v = load_ddf<Q, F, A, true>(ld_off(src + (size_t)opp(i) * plane, row + x));
                         if (fs & F_MOVING) {
                             const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                              VelSet<Q>::c[i][2] * L.wall_u[2]);
-                            v += (A)(6.0 * VelSet<Q>::w(i)) * cu;
+                            v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, true>()) * cu;
                         }
                         f[i] = v;
                     }
                 }
             }
-            collide<Q, COLL, A, (sizeof(T) >= 4)>(L, f, fo);
+            collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
 #pragma unroll
-            for (int i = 0; i < Q; i++) codes[k][i] = Codec<F>::template store<A>(fo[i], tab);
+            for (int i = 0; i < Q; i++) codes[k][i] = Codec<F>::template store_raw<A>(fo[i], tab);
         }
     }
     __syncthreads();
@@ -817,7 +857,7 @@ __device__ __forceinline__ void cell_moments(const LatDev& L, int parity, uint32
         make_rows(L, y, z, rc);
         const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
         const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
-        pull<Q, F, A>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+        pull<Q, F, A, false>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
         fields<Q, A>(f, rho, j);
         if (L.forced) {
             for (int a = 0; a < 3; a++) j[a] += (A)0.5 * (A)L.force[a];
