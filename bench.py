@@ -97,6 +97,57 @@ def measure_format(storage, n, steps, warmup):
             "launch": {k: cfg[k] for k in ("block", "cells_per_lane", "staged")}}
 
 
+def ensemble(storage="fp16s", count=256, steps=50, warmup=10):
+    """The batched workload: `count` independent D3Q19 BGK lattices with sizes
+    uniform in 32..96 per axis and tau uniform in [0.55, 1.0] (splitmix64,
+    seed 2112), half Taylor-Green, half Poiseuille.  MLUPs/s of one launch
+    per lattice per step, one batched launch per step, the persistent batched
+    launch, the batched launch replayed as a HIP graph of 100 steps, and the
+    autotuned configuration."""
+    import paper_2112_08926_amd as lbm
+    import lbm_workloads as wl
+    specs = wl.ensemble_specs(count=count, seed=2112, lo=32, hi=96)
+    params = [lbm.make_params(sp["nx"], sp["ny"], sp["nz"], q=19, collision="srt", storage=storage,
+                              tau=sp["tau"], force=sp["force"]) for sp in specs]
+    cells = sum(sp["nx"] * sp["ny"] * sp["nz"] for sp in specs)
+    g = lbm.Lattices(params)
+    try:
+        for k, sp in enumerate(specs):
+            flags, rho, u = wl.ensemble_member_inputs(sp)
+            g.set_boundaries(k, flags)
+            g.set_rho_u(k, rho, u)
+        out = {"lattices": count, "cells": cells, "storage": storage}
+        for name, cfg in [("per_lattice", dict(mode=0, block=128, cells_per_lane=1, staged=0, persistent=0,
+                                                 graph_steps=0)),
+                          ("batched", dict(mode=1, block=128, cells_per_lane=1, staged=0, persistent=0,
+                                           graph_steps=0)),
+                          ("persistent", dict(mode=1, block=128, cells_per_lane=1, staged=0, persistent=4,
+                                              graph_steps=0)),
+                          ("batched_graph100", dict(mode=1, block=128, cells_per_lane=1, staged=0, persistent=0,
+                                                    graph_steps=100))]:
+            g.set_launch(**cfg)
+            n = 100 if cfg["graph_steps"] else steps
+            ms = time_steps(g, n, warmup if not cfg["graph_steps"] else 100)
+            out[name + "_mlups"] = round(cells / (ms * 1e-3) / 1e6, 1)
+            print(f"[bench] ensemble {name}: {out[name + '_mlups']:.0f} MLUPs/s", file=sys.stderr, flush=True)
+        g.set_launch(graph_steps=0)
+        best = g.autotune(3)
+        g.set_launch(graph_steps=100)
+        ms = time_steps(g, 100, 100)
+        out["autotuned"] = {k: best[k] for k in ("mode", "block", "cells_per_lane", "staged", "persistent")}
+        out["autotuned_graph100_mlups"] = round(cells / (ms * 1e-3) / 1e6, 1)
+        print(f"[bench] ensemble autotuned {out['autotuned']}: {out['autotuned_graph100_mlups']:.0f} MLUPs/s",
+              file=sys.stderr, flush=True)
+        alg = 0
+        for sp in specs:
+            N = sp["nx"] * sp["ny"] * sp["nz"]
+            alg += N * (2 * 19 * ddf_bytes(storage) + 1)
+        out["autotuned_GBps_upper"] = round(alg / (ms * 1e-3) / 1e9, 1)
+        return out
+    finally:
+        g.close()
+
+
 def copy_bandwidth(nbytes=4 << 30, reps=10):
     """Achievable HBM bandwidth of a plain device copy (the library's copy
     probe), counted as bytes read + bytes written."""
@@ -181,6 +232,7 @@ def main():
     ap.add_argument("--formats", default="all", help="'all', 'headline' or a comma list")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-lattice ensemble")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -209,6 +261,10 @@ def main():
     if not args.no_accuracy:
         print("[bench] accuracy vs FP64 (64^3, 1000 steps)", file=sys.stderr, flush=True)
         acc = accuracy_vs_fp64([s for s in formats if s != "fp64"])
+    ens = None
+    if not args.no_ensemble:
+        print("[bench] ensemble of 256 lattices", file=sys.stderr, flush=True)
+        ens = ensemble()
     cpu = None
     if not args.no_cpu:
         print("[bench] CPU reference timing", file=sys.stderr, flush=True)
@@ -240,6 +296,7 @@ def main():
         "fp16s_vs_fp32_speedup": (round(head["mlups"] / results["fp32"]["mlups"], 3)
                                   if "fp32" in results else None),
         "l2_vs_fp64": acc,
+        "ensemble": ens,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line), flush=True)

@@ -86,7 +86,8 @@ typedef struct {
     int32_t collision;       /* lbm_collision */
     int32_t storage;         /* lbm_storage */
     int32_t arith;           /* lbm_arith */
-    int32_t reserved;        /* must be 0 */
+    int32_t unshifted;       /* 0: DDFs stored shifted, f_i - w_i (Sec. 2.2, the
+                                default); 1: ablation storing f_i itself */
     double tau;              /* relaxation time, > 0.5 (nu = (tau - 1/2)/3) */
     double trt_magic;        /* TRT Lambda = (tau - 1/2)(tau_minus - 1/2); 0.25 */
     double force[3];         /* Guo body force per volume (lattice units) */
@@ -144,8 +145,8 @@ typedef void (*lbm_free_fn)(void* ptr, void* ctx);
  * stream: a hipStream_t, or NULL for the null stream.  alloc/free_: optional
  * device allocator (both or neither); alloc_ctx is passed back to them.
  * Every cell starts as fluid at rest (rho = 1, u = 0).
- * Errors: LBM_EINVAL for tau <= 0.5, sizes out of range, reserved != 0 or
- * unknown enums; LBM_ENOMEM; LBM_EDEVICE. */
+ * Errors: LBM_EINVAL for tau <= 0.5, sizes out of range, unshifted not 0/1
+ * or unknown enums; LBM_ENOMEM; LBM_EDEVICE. */
 lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, void* stream,
                       lbm_alloc_fn alloc, lbm_free_fn free_, void* alloc_ctx,
                       lbm_handle** out);

@@ -36,7 +36,7 @@ class LbmError(RuntimeError):
 class LbmParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("q", ctypes.c_int32), ("collision", ctypes.c_int32), ("storage", ctypes.c_int32),
-                ("arith", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("arith", ctypes.c_int32), ("unshifted", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("trt_magic", ctypes.c_double),
                 ("force", ctypes.c_double * 3), ("wall_u", ctypes.c_double * 3),
                 ("eq_rho", ctypes.c_double), ("eq_u", ctypes.c_double * 3)]
@@ -144,9 +144,9 @@ def _host_ptr(a: np.ndarray | None):
 
 def make_params(nx, ny, nz, q=19, collision="srt", storage="fp32", arith="fp32", tau=0.6,
                 trt_magic=0.25, force=(0.0, 0.0, 0.0), wall_u=(0.0, 0.0, 0.0), eq_rho=1.0,
-                eq_u=(0.0, 0.0, 0.0)) -> LbmParams:
+                eq_u=(0.0, 0.0, 0.0), unshifted=False) -> LbmParams:
     return LbmParams(int(nx), int(ny), int(nz), int(q), COLLISION.get(collision, collision),
-                     STORAGE.get(storage, storage), ARITH.get(arith, arith), 0, float(tau),
+                     STORAGE.get(storage, storage), ARITH.get(arith, arith), int(bool(unshifted)), float(tau),
                      float(trt_magic), (ctypes.c_double * 3)(*force), (ctypes.c_double * 3)(*wall_u),
                      float(eq_rho), (ctypes.c_double * 3)(*eq_u))
 

@@ -27,6 +27,7 @@ struct LatDev {
     double wall_u[3];        // velocity of MOVING walls
     double eq_rho;           // state of EQ cells
     double eq_u[3];
+    double shift;            // 1: DDFs stored as f_i - w_i; 0: f_i (ablation)
     const void* eq_codes;    // q stored codes of the EQ cells' equilibrium
     int32_t forced;          // any force component != 0
     int32_t pad;

@@ -196,11 +196,11 @@ __device__ __forceinline__ A fields_sum(const A (&f)[Q]) {
 }
 
 template <int Q, class A>
-__device__ __forceinline__ void fields(const A (&f)[Q], A& rho, A (&j)[3]) {
+__device__ __forceinline__ void fields(const A (&f)[Q], A shift, A& rho, A (&j)[3]) {
     A r = f[0];
 #pragma unroll
     for (int i = 1; i < Q; i++) r += f[i];
-    rho = r + (A)1;                                          // the 1 of the shift last
+    rho = r + shift;                                         // the 1 of the shift last
     fields_j<Q, A>(f, j);
 }
 
@@ -233,9 +233,10 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
     A j[3];
     const A r = fields_sum<Q, A>(f);                         // raw units
     fields_j<Q, A>(f, j);
+    const A shift = (A)L.shift;                              // 1, or 0 without DDF shifting
     A rho;                                                   // the 1 of the shift added last
-    if constexpr (E == 0) rho = r + (A)1;
-    else rho = fmaa(r, (A)(1.0 / kSc), (A)1);
+    if constexpr (E == 0) rho = r + shift;
+    else rho = fmaa(r, (A)(1.0 / kSc), shift);
     const bool forced = L.forced != 0;
     const A Fx = (A)L.force[0], Fy = (A)L.force[1], Fz = (A)L.force[2];
     if (forced) {
@@ -257,7 +258,7 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
         uz = clamp_c(j[2] * inv);
     }
     const A C = (A)(-3) * fmaa(ux, ux, fmaa(uy, uy, uz * uz));
-    const A rhom1 = rho - (A)1;
+    const A rhom1 = rho - shift;                             // rho - 1 (shifted) or rho
     const A u3x = (A)3 * ux, u3y = (A)3 * uy, u3z = (A)3 * uz;
     const A w = (A)L.omega, wm = (A)L.omega_m;
     const A uF = fmaa(ux, Fx, fmaa(uy, Fy, uz * Fz));
@@ -780,9 +781,10 @@ __global__ void __launch_bounds__(512) k_step_batched(const LatDev* __restrict__
 // ------------------------------------------------------------ initialisation
 // Stored code of direction i of the (shifted) equilibrium of rho, u.
 template <int Q, int F, class A>
-__device__ __forceinline__ typename Codec<F>::T eq_code(int i, A rho, A ux, A uy, A uz, const EncEntry* tab) {
+__device__ __forceinline__ typename Codec<F>::T eq_code(int i, A rho, A ux, A uy, A uz, A shift,
+                                                       const EncEntry* tab) {
     const A C = (A)(-3) * (ux * ux + uy * uy + uz * uz);
-    const A rhom1 = rho - (A)1;
+    const A rhom1 = rho - shift;
     const A wi = (A)VelSet<Q>::w(i);
     const A B = (A)3 * cdot_i<Q, A>(i, ux, uy, uz);
     return Codec<F>::template store<A>(fmaa(wi * rho, fmaa((A)0.5, fmaa(B, B, C), B), wi * rhom1), tab);
@@ -797,7 +799,7 @@ __global__ void __launch_bounds__(64) k_eq_codes(LatDev L, typename Codec<F>::T*
     __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
     const int i = threadIdx.x;
-    if (i < Q) out[i] = eq_code<Q, F, A>(i, (A)L.eq_rho, (A)L.eq_u[0], (A)L.eq_u[1], (A)L.eq_u[2], tab);
+    if (i < Q) out[i] = eq_code<Q, F, A>(i, (A)L.eq_rho, (A)L.eq_u[0], (A)L.eq_u[1], (A)L.eq_u[2], (A)L.shift, tab);
 }
 
 // DDFs of the (shifted) equilibrium of rho, u (the paper's initialize kernel)
@@ -822,7 +824,7 @@ __global__ void __launch_bounds__(256) k_init(LatDev L, const double* __restrict
     T* d1 = (T*)L.f[1];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        T code = eq_code<Q, F, A>(i, rho, ux, uy, uz, tab);
+        T code = eq_code<Q, F, A>(i, rho, ux, uy, uz, (A)L.shift, tab);
         if (fl & F_EQ) code = eqc[i];
         if (fl & F_SOLID) code = Codec<F>::template store<A>((A)0, tab);
         d0[(size_t)i * L.plane + n] = code;
@@ -851,14 +853,14 @@ __device__ __forceinline__ void cell_moments(const LatDev& L, int parity, uint32
     if (fl & F_EQ) {
 #pragma unroll
         for (int i = 0; i < Q; i++) f[i] = Codec<F>::template load<A>(src[(size_t)i * L.plane + n]);
-        fields<Q, A>(f, rho, j);
+        fields<Q, A>(f, (A)L.shift, rho, j);
     } else {
         RowCtx rc;
         make_rows(L, y, z, rc);
         const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
         const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
         pull<Q, F, A, false>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
-        fields<Q, A>(f, rho, j);
+        fields<Q, A>(f, (A)L.shift, rho, j);
         if (L.forced) {
             for (int a = 0; a < 3; a++) j[a] += (A)0.5 * (A)L.force[a];
         }
@@ -960,7 +962,8 @@ __global__ void __launch_bounds__(256) k_diag(LatDev L, int parity, const double
                 const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
                 if (!(fs & F_SOLID)) continue;
                 const int o = opp(i);
-                const double fo = (double)Codec<F>::template load<A>(src[(size_t)o * L.plane + n]) + VelSet<Q>::w(o);
+                const double fo = (double)Codec<F>::template load<A>(src[(size_t)o * L.plane + n]) +
+                                  VelSet<Q>::w(o) * L.shift;
                 double mv = 0.0;
                 if (fs & F_MOVING)
                     mv = 6.0 * VelSet<Q>::w(i) * (VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +

@@ -273,6 +273,7 @@ static void fill_dev(Lattice& L, int arith) {
         d.eq_u[a] = L.p.eq_u[a];
     }
     d.eq_rho = L.p.eq_rho;
+    d.shift = L.p.unshifted ? 0.0 : 1.0;
     d.forced = (L.p.force[0] != 0.0 || L.p.force[1] != 0.0 || L.p.force[2] != 0.0) ? 1 : 0;
 }
 
@@ -281,7 +282,7 @@ static lbm_status check_params(const lbm_params& p, int k) {
     if (p.collision != LBM_SRT && p.collision != LBM_TRT) return fail(LBM_EINVAL, "lattice %d: unknown collision", k);
     if (p.storage < LBM_FP64 || p.storage > LBM_P16_2C) return fail(LBM_EINVAL, "lattice %d: unknown storage", k);
     if (p.arith != LBM_ARITH_FP32 && p.arith != LBM_ARITH_FP64) return fail(LBM_EINVAL, "lattice %d: unknown arith", k);
-    if (p.reserved != 0) return fail(LBM_EINVAL, "lattice %d: reserved field must be 0", k);
+    if (p.unshifted != 0 && p.unshifted != 1) return fail(LBM_EINVAL, "lattice %d: unshifted must be 0 or 1", k);
     if (!(p.tau > 0.5) || !std::isfinite(p.tau)) return fail(LBM_EINVAL, "lattice %d: tau must be > 0.5", k);
     if (p.collision == LBM_TRT && !(p.trt_magic > 0.0)) return fail(LBM_EINVAL, "lattice %d: trt_magic must be > 0", k);
     if (p.nx < 1 || p.ny < 1 || p.nz < 1 || p.nx > 65535 || p.ny > 65535 || p.nz > 65535)
