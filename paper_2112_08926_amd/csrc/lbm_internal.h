@@ -19,6 +19,7 @@ enum Storage : int { S_FP64 = 0, S_FP32 = 1, S_FP16 = 2, S_FP16S = 3, S_FP16C = 
 struct LatDev {
     void* f[2];              // DDF buffers: q planes of `plane` elements each
     const uint8_t* flags;    // one byte per cell
+    const uint32_t* wall_mask; // per cell: bit i = source x - c_i is a wall, bit 31 = one of them moves
     uint32_t nx, ny, nz;
     uint32_t plane;          // elements between consecutive direction planes
     double omega;            // 1/tau (TRT: symmetric rate)

@@ -153,15 +153,18 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
     }
     if (__any(near)) {
         // A wall source hands back what this cell sent towards it last step.
+        const uint32_t m = near ? ld_off(L.wall_mask, n) : 0u;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
-            if (near && (fs & F_SOLID)) {
+            if (m & (1u << i)) {
                 A v = load_ddf<Q, F, A, RAW>(ld_off(src + (size_t)opp(i) * plane, n));
-                if (fs & F_MOVING) {
-                    const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
-                                     VelSet<Q>::c[i][2] * L.wall_u[2]);
-                    v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, RAW>()) * cu;
+                if (m & 0x80000000u) {
+                    const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
+                    if (fs & F_MOVING) {
+                        const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                         VelSet<Q>::c[i][2] * L.wall_u[2]);
+                        v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, RAW>()) * cu;
+                    }
                 }
                 f[i] = v;
             }
@@ -555,15 +558,18 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
             const uint32_t xk = x + k;
             const uint32_t xkm = xk == 0 ? nx - 1 : xk - 1;
             const uint32_t xkp = xk + 1 == nx ? 0 : xk + 1;
+            const uint32_t m = near[k] ? ld_off(L.wall_mask, row + xk) : 0u;
 #pragma unroll
             for (int i = 1; i < Q; i++) {
-                const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, xk, xkm, xkp)];
-                if (near[k] && (fs & F_SOLID)) {
+                if (m & (1u << i)) {
                     A v = load_ddf<Q, F, A, true>(src[(size_t)opp(i) * plane + row + xk]);
-                    if (fs & F_MOVING) {
-                        const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
-                                         VelSet<Q>::c[i][2] * L.wall_u[2]);
-                        v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, true>()) * cu;
+                    if (m & 0x80000000u) {
+                        const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, xk, xkm, xkp)];
+                        if (fs & F_MOVING) {
+                            const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                             VelSet<Q>::c[i][2] * L.wall_u[2]);
+                            v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, true>()) * cu;
+                        }
                     }
                     f[i] = v;
                 }
@@ -680,17 +686,20 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
                 const uint32_t x = x0 + xl;
                 const uint32_t xm = x == 0 ? nx - 1 : x - 1;
                 const uint32_t xp = x + 1 == nx ? 0 : x + 1;
+                const uint32_t m = near ? ld_off(L.wall_mask, row + x) : 0u;
                 RowCtx rc;
                 make_rows(L, y, z, rc);
 #pragma unroll
                 for (int i = 1; i < Q; i++) {
-                    const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
-                    if (near && (fs & F_SOLID)) {
+                    if (m & (1u << i)) {
                         A v = load_ddf<Q, F, A, true>(ld_off(src + (size_t)opp(i) * plane, row + x));
-                        if (fs & F_MOVING) {
-                            const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
-                                             VelSet<Q>::c[i][2] * L.wall_u[2]);
-                            v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, true>()) * cu;
+                        if (m & 0x80000000u) {
+                            const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
+                            if (fs & F_MOVING) {
+                                const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                                 VelSet<Q>::c[i][2] * L.wall_u[2]);
+                                v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, true>()) * cu;
+                            }
                         }
                         f[i] = v;
                     }

@@ -168,26 +168,33 @@ __global__ void __launch_bounds__(256) k_decode(int storage, const uint16_t* __r
 }
 
 // NEAR bit of every fluid cell with a SOLID cell among its q-1 periodic
-// neighbours; reads the caller's flags from `raw`, writes `out`.
+// neighbours, and its wall mask (bit i: the source x - c_i is SOLID; bit 31:
+// one of those sources is MOVING); reads the caller's flags from `raw`.
 template <int Q>
 __global__ void __launch_bounds__(256) k_mark_near(const uint8_t* __restrict__ raw, uint8_t* __restrict__ out,
-                                                   uint32_t nx, uint32_t ny, uint32_t nz) {
+                                                   uint32_t* __restrict__ mask, uint32_t nx, uint32_t ny,
+                                                   uint32_t nz) {
     const size_t N = (size_t)nx * ny * nz;
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     uint8_t f = raw[n];
+    uint32_t m = 0;
     if (!(f & (F_SOLID | F_EQ))) {
         const uint32_t x = (uint32_t)(n % nx), yz = (uint32_t)(n / nx), y = yz % ny, z = yz / ny;
-        bool near = false;
         for (int i = 1; i < Q; i++) {
             const uint32_t sx = (x + nx - VelSet<Q>::c[i][0]) % nx;
             const uint32_t sy = (y + ny - VelSet<Q>::c[i][1]) % ny;
             const uint32_t sz = (z + nz - VelSet<Q>::c[i][2]) % nz;
-            near |= (raw[sx + (size_t)nx * (sy + (size_t)ny * sz)] & F_SOLID) != 0;
+            const uint8_t fs = raw[sx + (size_t)nx * (sy + (size_t)ny * sz)];
+            if (fs & F_SOLID) {
+                m |= 1u << i;
+                if (fs & F_MOVING) m |= 0x80000000u;
+            }
         }
-        if (near) f |= F_NEAR;
+        if (m) f |= F_NEAR;
     }
     out[n] = f;
+    mask[n] = m;
 }
 
 __global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
@@ -202,6 +209,7 @@ struct Lattice {
     uint32_t plane = 0;
     void* f[2] = {nullptr, nullptr};
     uint8_t* flags = nullptr;
+    uint32_t* wall_mask = nullptr;
     void* eq_codes = nullptr;   // q codes of the EQ state
     LatDev dev{};
 };
@@ -260,6 +268,7 @@ static void fill_dev(Lattice& L, int arith) {
     d.f[0] = L.f[0];
     d.f[1] = L.f[1];
     d.flags = L.flags;
+    d.wall_mask = L.wall_mask;
     d.eq_codes = L.eq_codes;
     d.nx = (uint32_t)L.p.nx;
     d.ny = (uint32_t)L.p.ny;
@@ -349,12 +358,14 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
         L.f[0] = dev_alloc(h, bytes);
         L.f[1] = dev_alloc(h, bytes);
         L.flags = (uint8_t*)dev_alloc(h, L.N);
+        L.wall_mask = (uint32_t*)dev_alloc(h, L.N * 4);
         L.eq_codes = dev_alloc(h, 27 * 8);
-        if (!L.f[0] || !L.f[1] || !L.flags || !L.eq_codes) {
+        if (!L.f[0] || !L.f[1] || !L.flags || !L.wall_mask || !L.eq_codes) {
             lbm_destroy(h);
             return fail(LBM_ENOMEM, "device allocation of lattice %d (%zu bytes per buffer) failed", k, bytes);
         }
         if (hipMemsetAsync(L.flags, 0, L.N, h->stream) != hipSuccess ||
+            hipMemsetAsync(L.wall_mask, 0, L.N * 4, h->stream) != hipSuccess ||
             hipMemsetAsync(L.f[0], 0, bytes, h->stream) != hipSuccess ||
             hipMemsetAsync(L.f[1], 0, bytes, h->stream) != hipSuccess) {
             lbm_destroy(h);
@@ -397,6 +408,7 @@ extern "C" void lbm_destroy(lbm_handle* h) {
         dev_free(h, L.f[0]);
         dev_free(h, L.f[1]);
         dev_free(h, L.flags);
+        dev_free(h, L.wall_mask);
         dev_free(h, L.eq_codes);
     }
     dev_free(h, h->d_partials);
@@ -537,9 +549,11 @@ extern "C" lbm_status lbm_set_boundaries(lbm_handle* h, int32_t k, const uint8_t
     if (e == hipSuccess) {
         const dim3 grid((unsigned)((L.N + 255) / 256));
         if (h->q == 19)
-            hipLaunchKernelGGL(k_mark_near<19>, grid, dim3(256), 0, h->stream, d_raw, L.flags, L.dev.nx, L.dev.ny, L.dev.nz);
+            hipLaunchKernelGGL(k_mark_near<19>, grid, dim3(256), 0, h->stream, d_raw, L.flags, L.wall_mask, L.dev.nx,
+                               L.dev.ny, L.dev.nz);
         else
-            hipLaunchKernelGGL(k_mark_near<27>, grid, dim3(256), 0, h->stream, d_raw, L.flags, L.dev.nx, L.dev.ny, L.dev.nz);
+            hipLaunchKernelGGL(k_mark_near<27>, grid, dim3(256), 0, h->stream, d_raw, L.flags, L.wall_mask, L.dev.nx,
+                               L.dev.ny, L.dev.nz);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // fl is a local buffer
