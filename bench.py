@@ -101,9 +101,10 @@ def ensemble(storage="fp16s", count=256, steps=50, warmup=10):
     """The batched workload: `count` independent D3Q19 BGK lattices with sizes
     uniform in 32..96 per axis and tau uniform in [0.55, 1.0] (splitmix64,
     seed 2112), half Taylor-Green, half Poiseuille.  MLUPs/s of one launch
-    per lattice per step, one batched launch per step, the persistent batched
-    launch, the batched launch replayed as a HIP graph of 100 steps, and the
-    autotuned configuration."""
+    per lattice per step, one batched launch per step over row tiles and over
+    cell-contiguous tiles, the persistent batched launch (8 workgroups of 256
+    per CU: full occupancy), the same replayed as a HIP graph of 100 steps,
+    and the autotuned configuration."""
     import paper_2112_08926_amd as lbm
     import lbm_workloads as wl
     specs = wl.ensemble_specs(count=count, seed=2112, lo=32, hi=96)
@@ -119,12 +120,14 @@ def ensemble(storage="fp16s", count=256, steps=50, warmup=10):
         out = {"lattices": count, "cells": cells, "storage": storage}
         for name, cfg in [("per_lattice", dict(mode=0, block=128, cells_per_lane=1, staged=0, persistent=0,
                                                  graph_steps=0)),
-                          ("batched", dict(mode=1, block=128, cells_per_lane=1, staged=0, persistent=0,
+                          ("batched_rows", dict(mode=1, block=128, cells_per_lane=1, staged=0, persistent=0,
+                                                graph_steps=0)),
+                          ("batched", dict(mode=2, block=256, cells_per_lane=1, staged=0, persistent=0,
                                            graph_steps=0)),
-                          ("persistent", dict(mode=1, block=128, cells_per_lane=1, staged=0, persistent=4,
+                          ("persistent", dict(mode=2, block=256, cells_per_lane=1, staged=0, persistent=8,
                                               graph_steps=0)),
-                          ("batched_graph100", dict(mode=1, block=128, cells_per_lane=1, staged=0, persistent=0,
-                                                    graph_steps=100))]:
+                          ("persistent_graph100", dict(mode=2, block=256, cells_per_lane=1, staged=0,
+                                                       persistent=8, graph_steps=100))]:
             g.set_launch(**cfg)
             n = 100 if cfg["graph_steps"] else steps
             ms = time_steps(g, n, warmup if not cfg["graph_steps"] else 100)

@@ -110,7 +110,12 @@ typedef struct {
 } lbm_diag;
 
 /* How lbm_step launches the stream-collide kernel. */
-typedef enum { LBM_LAUNCH_PER_LATTICE = 0, LBM_LAUNCH_BATCHED = 1 } lbm_launch_mode;
+/* PER_LATTICE: one launch per lattice per step over row tiles.  BATCHED:
+ * one launch per step over a table of row tiles (block * cells_per_lane cells
+ * of one row) of every lattice.  DENSE: one launch per step over tiles of
+ * `block` consecutive cells in index order, which may span rows, so short
+ * rows leave no lanes idle (one cell per lane, not staged). */
+typedef enum { LBM_LAUNCH_PER_LATTICE = 0, LBM_LAUNCH_BATCHED = 1, LBM_LAUNCH_DENSE = 2 } lbm_launch_mode;
 typedef struct {
     int32_t mode;            /* lbm_launch_mode */
     int32_t block;           /* threads per workgroup: 64, 128, 256, 512 */
@@ -121,7 +126,7 @@ typedef struct {
     int32_t staged;          /* 1: LDS-staged kernel (row segments moved with
                                 16-byte accesses); every nx must be a multiple
                                 of 16 / bytes per DDF */
-    int32_t persistent;      /* batched only: workgroups per CU of a persistent
+    int32_t persistent;      /* BATCHED/DENSE: workgroups per CU of a persistent
                                 grid walking the tile table; 0 = one workgroup
                                 per tile */
     int32_t graph_steps;     /* > 0 (even): lbm_step replays a HIP graph of

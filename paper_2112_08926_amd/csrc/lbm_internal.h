@@ -31,11 +31,13 @@ struct LatDev {
     double shift;            // 1: DDFs stored as f_i - w_i; 0: f_i (ablation)
     const void* eq_codes;    // q stored codes of the EQ cells' equilibrium
     int32_t forced;          // any force component != 0
+    float inv_nx, inv_ny;    // 1/nx, 1/ny rounded to float (cell-contiguous tiles)
     int32_t pad;
 };
 
 // One workgroup's share of a batched step: cells x0 .. x0+T-1 of row (y, z)
-// of lattice `lat`.
+// of lattice `lat`; for cell-contiguous tiles, the T cells that follow
+// (x0, y, z) in index order, across rows and z-planes.
 struct Tile {
     uint16_t lat, x0, y, z;
 };
@@ -50,6 +52,7 @@ struct StepLaunch {
     int q, storage, arith, collision;
     int block, cpl;
     int staged;              // LDS-staged kernel (cpl = cells per thread)
+    int dense;               // batched over cell-contiguous tiles of `block` cells
     int parity;
     const LatDev* lats;      // batched: device array of descriptors
     const Tile* tiles;       // batched: device array of tiles

@@ -119,15 +119,24 @@ __device__ __forceinline__ uint32_t src_x(int i, uint32_t x, uint32_t xm, uint32
 // is formed in 32 bits so that the load/store can use a scalar 64-bit base
 // plus a 32-bit per-lane offset (no 64-bit address arithmetic per lane).
 // Every offset here is below 2^32 bytes (N * bytes per DDF < 2^32).
+// The pointers are in the global address space: every buffer of the library
+// is device memory.  Saying so matters where a pointer comes from a
+// descriptor table in memory rather than a kernel argument; the compiler
+// would otherwise emit flat instructions.
+#define LBM_GLOBAL __attribute__((address_space(1)))
+// Clang vector types for wide accesses (HIP's uint2/uint4 are classes whose
+// copy constructor takes a generic reference, which loses the address space).
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ __forceinline__ T ld_off(const T* base, uint32_t idx) {
-    return *(const T*)((const char*)base + (uint32_t)(idx * (uint32_t)sizeof(T)));
+    return *(const LBM_GLOBAL T*)((const LBM_GLOBAL char*)base + (uint32_t)(idx * (uint32_t)sizeof(T)));
 }
 // New DDFs are streamed out: nontemporal stores (each element is written
 // once per step and read back only by the next step).
 template <class T>
 __device__ __forceinline__ void st_off(T* base, uint32_t idx, T v) {
-    __builtin_nontemporal_store(v, (T*)((char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))));
+    __builtin_nontemporal_store(v, (LBM_GLOBAL T*)((LBM_GLOBAL char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))));
 }
 
 // RAW: values in the storage's raw units (2^-kRawExp), as the step uses them;
@@ -140,7 +149,10 @@ __device__ __forceinline__ A load_ddf(typename Codec<F>::T v) {
 template <int F, bool RAW>
 constexpr double raw_scale() { return RAW ? (double)(1u << Codec<F>::kRawExp) : 1.0; }
 
-template <int Q, int F, class A, bool RAW>
+// LANE_ROWS: the row bases differ between lanes (cell-contiguous tiles), so
+// the whole in-plane index is the per-lane offset; otherwise the row base
+// is wavefront-uniform and folded into the scalar base address.
+template <int Q, int F, class A, bool RAW, bool LANE_ROWS = false>
 __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
                                      const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp,
                                      uint32_t n, bool near, A (&f)[Q]) {
@@ -148,8 +160,12 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
     const size_t plane = L.plane;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-        const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
-        f[i] = load_ddf<Q, F, A, RAW>(ld_off(p, src_x<Q>(i, x, xm, xp)));
+        if constexpr (LANE_ROWS) {
+            f[i] = load_ddf<Q, F, A, RAW>(ld_off(src + (size_t)i * plane, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)));
+        } else {
+            const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
+            f[i] = load_ddf<Q, F, A, RAW>(ld_off(p, src_x<Q>(i, x, xm, xp)));
+        }
     }
     if (__any(near)) {
         // A wall source hands back what this cell sent towards it last step.
@@ -159,7 +175,7 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
             if (m & (1u << i)) {
                 A v = load_ddf<Q, F, A, RAW>(ld_off(src + (size_t)opp(i) * plane, n));
                 if (m & 0x80000000u) {
-                    const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
+                    const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
                     if (fs & F_MOVING) {
                         const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                          VelSet<Q>::c[i][2] * L.wall_u[2]);
@@ -331,7 +347,7 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     RowCtx rc;
     make_rows(L, y, z, rc);
     const uint32_t n = rc.rows[4] + x;
-    const uint8_t fl = L.flags[n];
+    const uint8_t fl = ld_off(L.flags, n);
     if (fl & (F_SOLID | F_EQ)) return;
     const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
     const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
@@ -347,6 +363,51 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
         T* p = dst + ((size_t)i * plane + rc.rows[4]);
         st_off(p, x, Codec<F>::template store_raw<A>(fo[i], tab));
     }
+}
+
+// ------------------------------------------------------------ cell-contiguous tiles
+// q = a / d for a < 2^17, d <= 65535: the float quotient with the rounded
+// reciprocal is within one of q (its relative error is ~2^-23, and
+// a / d < 2^17), and one remainder test on each side makes it exact.
+__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t d, float inv_d) {
+    uint32_t q = (uint32_t)((float)a * inv_d);
+    int r = (int)a - (int)(q * d);
+    if (r < 0) { q -= 1; r += (int)d; }
+    if (r >= (int)d) q += 1;
+    return q;
+}
+
+// One cell per lane; the workgroup's cells follow (x0, y0, z0) in index
+// order, so short rows pack without idle lanes.  Lanes find their own
+// (x, y, z) and neighbour rows; the rest is the row tile's step.
+template <int Q, int F, class A, int COLL>
+__device__ __forceinline__ void step_tile_dense(const LatDev& L, uint32_t x0, uint32_t y0, uint32_t z0,
+                                                int parity, const EncEntry* tab) {
+    using T = typename Codec<F>::T;
+    uint32_t x = x0 + threadIdx.x;                           // < nx + 512
+    const uint32_t dy = div_small(x, L.nx, L.inv_nx);
+    x -= dy * L.nx;
+    uint32_t y = y0 + dy;                                    // < ny + 512
+    const uint32_t dz = div_small(y, L.ny, L.inv_ny);
+    y -= dz * L.ny;
+    const uint32_t z = z0 + dz;
+    if (z >= L.nz) return;                                   // past the lattice's last cell
+    RowCtx rc;
+    make_rows(L, y, z, rc);
+    const uint32_t n = rc.rows[4] + x;
+    const uint8_t fl = ld_off(L.flags, n);
+    if (fl & (F_SOLID | F_EQ)) return;
+    const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
+    const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+    const T* __restrict__ src = (const T*)L.f[parity];
+    T* __restrict__ dst = (T*)L.f[parity ^ 1];
+
+    A f[Q], fo[Q];
+    pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+    collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
+    const size_t plane = L.plane;
+#pragma unroll
+    for (int i = 0; i < Q; i++) st_off(dst + (size_t)i * plane, n, Codec<F>::template store_raw<A>(fo[i], tab));
 }
 
 // ------------------------------------------------------------ several cells per lane
@@ -369,15 +430,15 @@ __device__ __forceinline__ RowVec<T, CPL> vload(const T* p) {
     RowVec<T, CPL> r;
     constexpr int W = RowVec<T, CPL>::W;
     if constexpr (W == 1) {
-        r.w[0] = *(const uint32_t*)p;
+        r.w[0] = *(const LBM_GLOBAL uint32_t*)p;
     } else if constexpr (W == 2) {
-        const uint2 v = *(const uint2*)p;
+        const u32x2 v = *(const LBM_GLOBAL u32x2*)p;
         r.w[0] = v.x; r.w[1] = v.y;
     } else {
         static_assert(W % 4 == 0, "row vector width");
 #pragma unroll
         for (int k = 0; k < W / 4; k++) {
-            const uint4 v = ((const uint4*)p)[k];
+            const u32x4 v = ((const LBM_GLOBAL u32x4*)p)[k];
             r.w[4 * k] = v.x; r.w[4 * k + 1] = v.y; r.w[4 * k + 2] = v.z; r.w[4 * k + 3] = v.w;
         }
     }
@@ -388,13 +449,13 @@ template <class T, int CPL>
 __device__ __forceinline__ void vstore(T* p, const RowVec<T, CPL>& r) {
     constexpr int W = RowVec<T, CPL>::W;
     if constexpr (W == 1) {
-        *(uint32_t*)p = r.w[0];
+        *(LBM_GLOBAL uint32_t*)p = r.w[0];
     } else if constexpr (W == 2) {
-        *(uint2*)p = make_uint2(r.w[0], r.w[1]);
+        *(LBM_GLOBAL u32x2*)p = u32x2{r.w[0], r.w[1]};
     } else {
 #pragma unroll
         for (int k = 0; k < W / 4; k++)
-            ((uint4*)p)[k] = make_uint4(r.w[4 * k], r.w[4 * k + 1], r.w[4 * k + 2], r.w[4 * k + 3]);
+            ((LBM_GLOBAL u32x4*)p)[k] = u32x4{r.w[4 * k], r.w[4 * k + 1], r.w[4 * k + 2], r.w[4 * k + 3]};
     }
 }
 
@@ -490,9 +551,9 @@ __device__ __forceinline__ T shfl_elem_down(T v) {
 
 template <int CPL>
 __device__ __forceinline__ uint32_t load_flags(const uint8_t* p) {
-    if constexpr (CPL == 1) return *p;
-    else if constexpr (CPL == 2) return *(const uint16_t*)p;
-    else return *(const uint32_t*)p;
+    if constexpr (CPL == 1) return *(const LBM_GLOBAL uint8_t*)p;
+    else if constexpr (CPL == 2) return *(const LBM_GLOBAL uint16_t*)p;
+    else return *(const LBM_GLOBAL uint32_t*)p;
 }
 
 template <int Q, int F, class A, int COLL, int CPL>
@@ -536,11 +597,11 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
         const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
         const RV v = vload<T, CPL>(p + x);
         if (VelSet<Q>::c[i][0] > 0) {
-            const T edge = p[xm];
+            const T edge = ld_off(p, xm);
             const T prev = shfl_elem_up<T>(velem<T, CPL>(v, CPL - 1));
             raw[i] = shift_up<T, CPL>(v, first_lane ? edge : prev);
         } else if (VelSet<Q>::c[i][0] < 0) {
-            const T edge = p[xn];
+            const T edge = ld_off(p, xn);
             const T next = shfl_elem_down<T>(velem<T, CPL>(v, 0));
             raw[i] = shift_down<T, CPL>(v, last_lane ? edge : next);
         } else {
@@ -562,9 +623,9 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
 #pragma unroll
             for (int i = 1; i < Q; i++) {
                 if (m & (1u << i)) {
-                    A v = load_ddf<Q, F, A, true>(src[(size_t)opp(i) * plane + row + xk]);
+                    A v = load_ddf<Q, F, A, true>(ld_off(src + (size_t)opp(i) * plane, row + xk));
                     if (m & 0x80000000u) {
-                        const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, xk, xkm, xkp)];
+                        const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, xk, xkm, xkp));
                         if (fs & F_MOVING) {
                             const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                              VelSet<Q>::c[i][2] * L.wall_u[2]);
@@ -586,7 +647,7 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
             T* p = dst + ((size_t)i * plane + row + x);
 #pragma unroll
             for (int k = 0; k < CPL; k++)
-                if (!special[k]) p[k] = velem<T, CPL>(out[i], k);
+                if (!special[k]) *(LBM_GLOBAL T*)(p + k) = velem<T, CPL>(out[i], k);
         }
     } else {
 #pragma unroll
@@ -651,15 +712,15 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
         const T* rp = src + (size_t)i * plane + (sy + sz * ny) * nx + x0;
         T* lp = s_ddf + i * RS + OFF;
         for (uint32_t k = lane; k < nvec; k += 64)
-            *(uint4*)(lp + k * VE) = *(const uint4*)(rp + k * VE);
+            *(u32x4*)(lp + k * VE) = *(const LBM_GLOBAL u32x4*)(rp + k * VE);
         if (lane == 0 && cx != 0) {
             const T* r0 = rp - x0;
-            if (cx > 0) lp[-1] = r0[x0 == 0 ? nx - 1 : x0 - 1];
-            else lp[seg] = r0[x0 + seg == nx ? 0 : x0 + seg];
+            if (cx > 0) lp[-1] = ld_off(r0, x0 == 0 ? nx - 1 : x0 - 1);
+            else lp[seg] = ld_off(r0, x0 + seg == nx ? 0 : x0 + seg);
         }
     }
     for (uint32_t k = threadIdx.x; k < seg / 2; k += B)
-        ((uint16_t*)s_fl)[k] = ((const uint16_t*)(L.flags + row + x0))[k];
+        ((uint16_t*)s_fl)[k] = ((const LBM_GLOBAL uint16_t*)(L.flags + row + x0))[k];
     __syncthreads();
 
     // ---- collide the K cells of this thread
@@ -675,7 +736,7 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
             for (int i = 0; i < Q; i++) codes[k][i] = Codec<F>::template store<A>((A)0, tab);
         } else if (fl & F_EQ) {
 #pragma unroll
-            for (int i = 0; i < Q; i++) codes[k][i] = eqc[i];
+            for (int i = 0; i < Q; i++) codes[k][i] = ld_off(eqc, (uint32_t)i);
         } else {
             A f[Q], fo[Q];
 #pragma unroll
@@ -694,7 +755,7 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
                     if (m & (1u << i)) {
                         A v = load_ddf<Q, F, A, true>(ld_off(src + (size_t)opp(i) * plane, row + x));
                         if (m & 0x80000000u) {
-                            const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
+                            const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
                             if (fs & F_MOVING) {
                                 const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                                  VelSet<Q>::c[i][2] * L.wall_u[2]);
@@ -726,7 +787,7 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
         T* rp = dst + (size_t)i * plane + row + x0;
         const T* lp = s_ddf + i * RS + OFF;
         for (uint32_t k = lane; k < nvec; k += 64)
-            *(uint4*)(rp + k * VE) = *(const uint4*)(lp + k * VE);
+            *(LBM_GLOBAL u32x4*)(rp + k * VE) = *(const u32x4*)(lp + k * VE);
     }
     __syncthreads();                                        // LDS is reused by the next tile
 }
@@ -784,6 +845,18 @@ __global__ void __launch_bounds__(512) k_step_batched(const LatDev* __restrict__
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
         run_tile<Q, F, A, COLL, CPL>(lats[tl.lat], tl.x0, tl.y, tl.z, parity, tab);
+    }
+}
+
+template <int Q, int F, class A, int COLL>
+__global__ void __launch_bounds__(512) k_step_dense(const LatDev* __restrict__ lats,
+                                                    const Tile* __restrict__ tiles, uint32_t ntiles,
+                                                    int parity, const EncEntry* __restrict__ enc) {
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    const EncEntry* tab = stage_table<F>(enc, s_tab);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = tiles[t];
+        step_tile_dense<Q, F, A, COLL>(lats[tl.lat], tl.x0, tl.y, tl.z, parity, tab);
     }
 }
 
@@ -1009,6 +1082,12 @@ struct FormatLaunchers {
                            s.lats, s.tiles, s.ntiles, s.parity, s.enc);
         return hipGetLastError();
     }
+    template <int Q, class A, int COLL>
+    static hipError_t dense_k(const StepLaunch& s) {
+        hipLaunchKernelGGL((k_step_dense<Q, F, A, COLL>), dim3(s.grid), dim3(s.block), 0, s.stream, s.lats, s.tiles,
+                           s.ntiles, s.parity, s.enc);
+        return hipGetLastError();
+    }
     template <int Q, class A, int COLL, int K>
     static hipError_t staged_single_k(const StepLaunch& s, const LatDev& L) {
         using T = typename Codec<F>::T;
@@ -1044,6 +1123,7 @@ struct FormatLaunchers {
     }
     template <int Q, class A, int COLL>
     static hipError_t batched_qac(const StepLaunch& s) {
+        if (s.dense) return (s.cpl == 1 && !s.staged) ? dense_k<Q, A, COLL>(s) : hipErrorInvalidValue;
         if (s.staged) {
             if (s.cpl == 1) return staged_batched_k<Q, A, COLL, 1>(s);
             if (s.cpl == 2) return staged_batched_k<Q, A, COLL, 2>(s);

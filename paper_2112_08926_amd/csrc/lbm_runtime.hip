@@ -197,9 +197,13 @@ __global__ void __launch_bounds__(256) k_mark_near(const uint8_t* __restrict__ r
     mask[n] = m;
 }
 
-__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
+// One 16-byte element per lane, streamed with nontemporal loads and stores
+// (the fastest plain copy form measured on gfx950); grid-stride only beyond
+// 2^31 workgroups.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_copy(const f32x4* __restrict__ src, f32x4* __restrict__ dst, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // ------------------------------------------------------------------ handle
@@ -284,6 +288,8 @@ static void fill_dev(Lattice& L, int arith) {
     d.eq_rho = L.p.eq_rho;
     d.shift = L.p.unshifted ? 0.0 : 1.0;
     d.forced = (L.p.force[0] != 0.0 || L.p.force[1] != 0.0 || L.p.force[2] != 0.0) ? 1 : 0;
+    d.inv_nx = 1.0f / (float)L.p.nx;
+    d.inv_ny = 1.0f / (float)L.p.ny;
 }
 
 static lbm_status check_params(const lbm_params& p, int k) {
@@ -429,10 +435,20 @@ static lbm_status check_lattice(lbm_handle* h, int32_t k) {
 // of `block` cells, lattice by lattice, row by row.
 static lbm_status rebuild_tiles(lbm_handle* h) {
     const int T = h->launch.block * h->launch.cells_per_lane;
-    if (h->d_tiles && h->tiles_block == T) return LBM_OK;
+    const bool dense = h->launch.mode == LBM_LAUNCH_DENSE;
+    const int key = 2 * T + (dense ? 1 : 0);
+    if (h->d_tiles && h->tiles_block == key) return LBM_OK;
     std::vector<Tile> tiles;
     for (size_t k = 0; k < h->lats.size(); k++) {
         const lbm_params& p = h->lats[k].p;
+        if (dense) {
+            // T consecutive cells each, from the start cell's coordinates
+            const size_t N = h->lats[k].N, row = (size_t)p.nx, slab = row * p.ny;
+            for (size_t n0 = 0; n0 < N; n0 += T)
+                tiles.push_back(Tile{(uint16_t)k, (uint16_t)(n0 % row), (uint16_t)((n0 / row) % p.ny),
+                                     (uint16_t)(n0 / slab)});
+            continue;
+        }
         for (int z = 0; z < p.nz; z++)
             for (int y = 0; y < p.ny; y++)
                 for (int x0 = 0; x0 < p.nx; x0 += T)
@@ -445,7 +461,7 @@ static lbm_status rebuild_tiles(lbm_handle* h) {
     HIP_TRY(hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->ntiles = (uint32_t)tiles.size();
-    h->tiles_block = T;
+    h->tiles_block = key;
     return LBM_OK;
 }
 
@@ -459,6 +475,7 @@ static StepLaunch make_launch(lbm_handle* h, const lbm_launch& cfg, int parity) 
     s.block = cfg.block;
     s.cpl = cfg.cells_per_lane;
     s.staged = cfg.staged;
+    s.dense = cfg.mode == LBM_LAUNCH_DENSE ? 1 : 0;
     s.parity = parity;
     s.lats = h->d_lats;
     s.tiles = h->d_tiles;
@@ -473,7 +490,7 @@ static StepLaunch make_launch(lbm_handle* h, const lbm_launch& cfg, int parity) 
 // Enqueue one time step with the given configuration, reading buffer `parity`.
 static hipError_t enqueue_step(lbm_handle* h, const lbm_launch& cfg, int parity) {
     const StepLaunch s = make_launch(h, cfg, parity);
-    if (cfg.mode == LBM_LAUNCH_BATCHED) return launch_step_batched(s);
+    if (cfg.mode != LBM_LAUNCH_PER_LATTICE) return launch_step_batched(s);
     for (auto& L : h->lats) {
         hipError_t e = launch_step_single(s, L.dev);
         if (e != hipSuccess) return e;
@@ -689,9 +706,12 @@ extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_
 
 // ------------------------------------------------------------------ launch configuration
 static lbm_status check_launch(lbm_handle* h, const lbm_launch& c) {
-    if (c.mode != LBM_LAUNCH_PER_LATTICE && c.mode != LBM_LAUNCH_BATCHED) return fail(LBM_EINVAL, "unknown launch mode");
+    if (c.mode != LBM_LAUNCH_PER_LATTICE && c.mode != LBM_LAUNCH_BATCHED && c.mode != LBM_LAUNCH_DENSE)
+        return fail(LBM_EINVAL, "unknown launch mode");
     if (c.block != 64 && c.block != 128 && c.block != 256 && c.block != 512) return fail(LBM_EINVAL, "block must be 64..512");
     if (c.staged != 0 && c.staged != 1) return fail(LBM_EINVAL, "staged must be 0 or 1");
+    if (c.mode == LBM_LAUNCH_DENSE && (c.staged || c.cells_per_lane != 1))
+        return fail(LBM_EINVAL, "cell-contiguous tiles take one cell per lane and no staging");
     if (c.staged) {
         if (c.cells_per_lane != 1 && c.cells_per_lane != 2)
             return fail(LBM_EINVAL, "the staged kernel takes 1 or 2 cells per thread");
@@ -754,10 +774,11 @@ extern "C" lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launc
                 const lbm_launch c{LBM_LAUNCH_PER_LATTICE, b, cpl, staged, 0, keep.graph_steps};
                 if (check_launch(h, c) != LBM_OK) continue;
                 cands.push_back(c);
-                if (h->lats.size() > 1) {
-                    cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, staged, 0, keep.graph_steps});
-                    for (int pers : {2, 4, 8})
-                        cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, staged, pers, keep.graph_steps});
+                // persistent grids of half and full occupancy (2048 threads per CU)
+                const int pers[] = {0, 1024 / b, 2048 / b};
+                for (int pz : pers) {
+                    if (h->lats.size() > 1) cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, staged, pz, keep.graph_steps});
+                    if (cpl == 1 && !staged) cands.push_back({LBM_LAUNCH_DENSE, b, 1, 0, pz, keep.graph_steps});
                 }
             }
         }
@@ -850,9 +871,9 @@ extern "C" lbm_status lbm_copy_probe(const void* d_src, void* d_dst, size_t byte
         return fail(LBM_EINVAL, "copy probe needs 16-byte aligned pointers and size");
     const size_t n = bytes / 16;
     if (n == 0) return LBM_OK;
-    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (const float4*)d_src,
-                       (float4*)d_dst, n);
+    const size_t blocks = std::min<size_t>((n + 255) / 256, (size_t)1 << 31);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (const f32x4*)d_src,
+                       (f32x4*)d_dst, n);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
 }

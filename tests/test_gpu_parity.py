@@ -136,7 +136,10 @@ def test_batched_equals_per_lattice_and_graph(lbm, orc):
     results = {}
     for name, cfg in [("per_lattice", dict(mode=0, block=64)), ("batched", dict(mode=1, block=128)),
                       ("persistent", dict(mode=1, block=256, persistent=2)),
-                      ("graph", dict(mode=1, block=64, graph_steps=4))]:
+                      ("graph", dict(mode=1, block=64, graph_steps=4)),
+                      ("dense", dict(mode=2, block=128)),
+                      ("dense_persistent", dict(mode=2, block=64, persistent=3)),
+                      ("dense_graph", dict(mode=2, block=256, persistent=8, graph_steps=4))]:
         say("ensemble", name)
         with lbm.Lattices(params) as g:
             for k, (flags, rho, u) in enumerate(inputs):
@@ -146,7 +149,7 @@ def test_batched_equals_per_lattice_and_graph(lbm, orc):
             g.step(3)
             g.step(7)
             results[name] = [g.get_ddf(k) for k in range(len(params))]
-    for name in ("batched", "persistent", "graph"):
+    for name in ("batched", "persistent", "graph", "dense", "dense_persistent", "dense_graph"):
         for a, b in zip(results["per_lattice"], results[name]):
             assert np.array_equal(a, b), name
 
@@ -224,20 +227,22 @@ def test_cells_per_lane_bit_identical(lbm, orc, storage, cpl, staged, block, q, 
 
 
 def test_wrap_and_tiny_lattices(lbm, orc):
-    """Edge cases of the row decomposition: a 1x1x1 lattice (every neighbour
-    is the cell itself), a 2x3x1 lattice, and rows shorter than a wavefront,
-    against the reference after 5 steps (FP64)."""
+    """Edge cases of the row and cell-contiguous decompositions: a 1x1x1
+    lattice (every neighbour is the cell itself), a 2x3x1 lattice, and rows
+    shorter than a wavefront, against the reference after 5 steps (FP64)."""
     for (nx, ny, nz) in [(1, 1, 1), (2, 3, 1), (3, 1, 2), (65, 2, 3)]:
         N = nx * ny * nz
         rho, u = wl.random_fields(N, seed=nx + 7 * ny)
         ref = orc.Lattice(nx, ny, nz, q=19, tau=0.7, collision="trt").init(rho, u)
         ref.step(5)
-        with lbm.Lattices(lbm.make_params(nx, ny, nz, q=19, collision="trt", storage="fp64",
-                                          arith="fp64", tau=0.7)) as g:
-            g.set_rho_u(0, rho, u)
-            g.step(5)
-            f = g.get_ddf(0)
-        assert np.abs(f - ref.f).max() <= 1e-13 * max(np.abs(ref.f).max(), 1e-3), (nx, ny, nz)
+        for mode in (0, 2):
+            with lbm.Lattices(lbm.make_params(nx, ny, nz, q=19, collision="trt", storage="fp64",
+                                              arith="fp64", tau=0.7)) as g:
+                g.set_launch(mode=mode, block=64)
+                g.set_rho_u(0, rho, u)
+                g.step(5)
+                f = g.get_ddf(0)
+            assert np.abs(f - ref.f).max() <= 1e-13 * max(np.abs(ref.f).max(), 1e-3), (nx, ny, nz, mode)
 
 
 def test_invalid_launch_rejected(lbm):
@@ -248,6 +253,12 @@ def test_invalid_launch_rejected(lbm):
             g.set_launch(block=96)
         with pytest.raises(lbm.LbmError):
             g.set_launch(graph_steps=3)
+        with pytest.raises(lbm.LbmError):
+            g.set_launch(mode=2, cells_per_lane=2)   # cell-contiguous tiles: one cell per lane
+        with pytest.raises(lbm.LbmError):
+            g.set_launch(mode=2, staged=1)
+        with pytest.raises(lbm.LbmError):
+            g.set_launch(mode=3)
     with lbm.Lattices(lbm.make_params(32, 4, 4, storage="fp64", arith="fp64")) as g:
         with pytest.raises(lbm.LbmError):
             g.set_launch(cells_per_lane=2)
@@ -340,3 +351,30 @@ def test_unshifted_one_step(lbm, orc, storage):
     ref.step(1)
     same = assert_step_parity(orc, storage, out, ref.f, f"unshifted {storage}")
     say("  identical codes:", same)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16s", "fp16c", "p16_2c", "fp64"])
+@pytest.mark.parametrize("q,collision", [(19, "trt"), (27, "srt")])
+def test_dense_tiles_bit_identical(lbm, orc, storage, q, collision):
+    """Cell-contiguous tiles (spanning rows and z-planes, with a partial last
+    tile) give bit-identical states to row tiles, on a lattice with walls, a
+    moving lid, EQ cells and a force, in single, persistent and graph
+    launches."""
+    nx, ny, nz = 37, 6, 5
+    say("dense", storage, q, collision)
+    flags, rho, u = one_step_inputs(nx, ny, nz, q, seed=41 + q)
+    arith = "fp64" if storage == "fp64" else "fp32"
+    kw = dict(q=q, collision=collision, storage=storage, arith=arith, tau=0.58, force=(2e-5, 1e-5, 0.0),
+              wall_u=(0.0, 0.07, 0.0), eq_rho=1.01, eq_u=(0.03, 0.0, 0.0))
+    out = {}
+    for name, cfg in [("rows", dict(mode=0, block=256)), ("dense64", dict(mode=2, block=64)),
+                      ("dense512_pers", dict(mode=2, block=512, persistent=1)),
+                      ("dense128_graph", dict(mode=2, block=128, graph_steps=2))]:
+        with lbm.Lattices(lbm.make_params(nx, ny, nz, **kw)) as g:
+            g.set_boundaries(0, flags)
+            g.set_rho_u(0, rho, u)
+            g.set_launch(**cfg)
+            g.step(4)
+            out[name] = g.get_ddf(0)
+    for name in ("dense64", "dense512_pers", "dense128_graph"):
+        assert np.array_equal(out["rows"], out[name]), name
