@@ -57,7 +57,13 @@ typedef enum {
     LBM_ENONFINITE = -5     /* diagnostics found non-finite fields */
 } lbm_status;
 
-typedef enum { LBM_D3Q19 = 19, LBM_D3Q27 = 27 } lbm_velset;
+/* Velocity sets (Sec. 2.1, Table 1), named by their number of directions:
+ * rest first, then opposite pairs (2k-1, 2k).  D2Q9 needs nz = 1.  Several
+ * cells per lane and the LDS-staged kernel exist for D3Q19 and D3Q27.  (D3Q7
+ * and D3Q13 of Table 1 are not offered: with the equilibrium of Sec. 2.2
+ * D3Q7 does not conserve momentum (its c_s^2 is 1/4) and D3Q13 lacks the
+ * fourth-order isotropy of the viscous stress.) */
+typedef enum { LBM_D2Q9 = 9, LBM_D3Q15 = 15, LBM_D3Q19 = 19, LBM_D3Q27 = 27 } lbm_velset;
 typedef enum { LBM_SRT = 0, LBM_TRT = 1 } lbm_collision;
 
 /* DDF storage formats (Sec. 3, Table 2).  Codes of the 16-bit formats:

@@ -113,13 +113,14 @@ def store(fmt, values) -> np.ndarray:
 # velocity sets and equilibrium (Sec. 2.2)
 # --------------------------------------------------------------------------
 def velset(q: int):
-    """(c[q,3] int, w[q] float64, opp[q] int) of D3Q19 or D3Q27."""
+    """(c[q,3] int, w[q] float64, opp[q] int) of D3Q7, D2Q9 (q = 9, c_z = 0),
+    D3Q13, D3Q15, D3Q19 or D3Q27 (Table 1)."""
     c = np.zeros((q, 3), dtype=np.int32)
     w = np.zeros(q, dtype=np.float64)
     opp = np.zeros(q, dtype=np.int32)
     if lib().oracle_velset(q, _ptr(c, ctypes.c_int32), _ptr(w, ctypes.c_double),
                            _ptr(opp, ctypes.c_int32)) != 0:
-        raise ValueError(f"unsupported velocity set D3Q{q}")
+        raise ValueError(f"unsupported velocity set with {q} directions")
     return c, w, opp
 
 

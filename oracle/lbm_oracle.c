@@ -237,16 +237,56 @@ static const int C27[27][3] = {
     { 1, 1, 1}, {-1,-1,-1}, { 1, 1,-1}, {-1,-1, 1}, { 1,-1, 1}, {-1, 1,-1},
     {-1, 1, 1}, { 1,-1,-1}
 };
+/* READING for the other sets of Table 1 (only named there): the same
+ * conventions (rest first, then opposite pairs), the directions in the
+ * D3Q19/D3Q27 order restricted to the set.  D2Q9: the four axis directions
+ * in x and y and the four xy diagonals, weights 4/9, 1/9, 1/36.  D3Q7: rest
+ * and the six faces, weights 1/4, 1/8.  D3Q13: rest and the twelve edge
+ * directions, weights 1/2, 1/24.  D3Q15: rest, six faces, eight corners,
+ * weights 2/9, 1/9, 1/72.  Table 1's delta values of all four come out only
+ * with these weights and the equilibrium of Sec. 2.2 (checked by the tests). */
+static const int C9[9][3] = {
+    { 0, 0, 0}, { 1, 0, 0}, {-1, 0, 0}, { 0, 1, 0}, { 0,-1, 0},
+    { 1, 1, 0}, {-1,-1, 0}, { 1,-1, 0}, {-1, 1, 0}
+};
+static const int C13[13][3] = {
+    { 0, 0, 0},
+    { 1, 1, 0}, {-1,-1, 0}, { 1, 0, 1}, {-1, 0,-1}, { 0, 1, 1}, { 0,-1,-1},
+    { 1,-1, 0}, {-1, 1, 0}, { 1, 0,-1}, {-1, 0, 1}, { 0, 1,-1}, { 0,-1, 1}
+};
+static const int C15[15][3] = {
+    { 0, 0, 0},
+    { 1, 0, 0}, {-1, 0, 0}, { 0, 1, 0}, { 0,-1, 0}, { 0, 0, 1}, { 0, 0,-1},
+    { 1, 1, 1}, {-1,-1,-1}, { 1, 1,-1}, {-1,-1, 1}, { 1,-1, 1}, {-1, 1,-1},
+    {-1, 1, 1}, { 1,-1,-1}
+};
 
+static int valid_q(int q) { return q == 7 || q == 9 || q == 13 || q == 15 || q == 19 || q == 27; }
+
+/* direction table of a velocity set (D3Q7 and D3Q19 are prefixes of D3Q27) */
+static const int (*velocities(int q))[3]
+{
+    switch (q) {
+    case 9:  return C9;
+    case 13: return C13;
+    case 15: return C15;
+    default: return C27;
+    }
+}
+
+/* weight by the squared length of c_i */
 static double weight(int q, int i)
 {
-    const int len2 = C27[i][0] * C27[i][0] + C27[i][1] * C27[i][1] + C27[i][2] * C27[i][2];
-    if (q == 19) {
-        static const double w19[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
-        return w19[len2];
+    const int (*C)[3] = velocities(q);
+    const int len2 = C[i][0] * C[i][0] + C[i][1] * C[i][1] + C[i][2] * C[i][2];
+    switch (q) {
+    case 7:  return len2 == 0 ? 1.0 / 4.0 : 1.0 / 8.0;
+    case 9:  { static const double w[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0}; return w[len2]; }
+    case 13: return len2 == 0 ? 1.0 / 2.0 : 1.0 / 24.0;
+    case 15: { static const double w[4] = {2.0 / 9.0, 1.0 / 9.0, 0.0, 1.0 / 72.0}; return w[len2]; }
+    case 19: { static const double w[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0}; return w[len2]; }
+    default: { static const double w[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0}; return w[len2]; }
     }
-    static const double w27[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
-    return w27[len2];
 }
 
 /* opposite direction: pairs are (2k-1, 2k) */
@@ -254,9 +294,10 @@ static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 int oracle_velset(int q, int32_t *c, double *w, int32_t *opp)
 {
-    if (q != 19 && q != 27) return -1;
+    if (!valid_q(q)) return -1;
+    const int (*C)[3] = velocities(q);
     for (int i = 0; i < q; i++) {
-        for (int a = 0; a < 3; a++) c[3 * i + a] = C27[i][a];
+        for (int a = 0; a < 3; a++) c[3 * i + a] = C[i][a];
         w[i] = weight(q, i);
         opp[i] = opposite(i);
     }
@@ -272,11 +313,12 @@ int oracle_velset(int q, int32_t *c, double *w, int32_t *opp)
  * and D = w_i (rho - 1) are formed.  Unshifted: w_i rho (1/2 (B^2+C) + B + 1). */
 void oracle_equilibrium(int q, int shifted, double rho, const double *u, double *feq)
 {
+    const int (*cv)[3] = velocities(q);
     const double C = -3.0 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const double rhom1 = rho - 1.0;
     for (int i = 0; i < q; i++) {
         const double w = weight(q, i);
-        const double B = 3.0 * (u[0] * C27[i][0] + u[1] * C27[i][1] + u[2] * C27[i][2]);
+        const double B = 3.0 * (u[0] * cv[i][0] + u[1] * cv[i][1] + u[2] * cv[i][2]);
         if (shifted)
             feq[i] = fma(w * rho, fma(0.5, fma(B, B, C), B), w * rhom1);
         else
@@ -320,16 +362,17 @@ static void pull(const oracle_lattice *L, const double *f, const uint8_t *flags,
 {
     const int64_t N = (int64_t)L->nx * L->ny * L->nz;
     const int64_t n = cell(L, x, y, z);
+    const int (*cv)[3] = velocities(L->q);
     for (int i = 0; i < L->q; i++) {
-        const int sx = wrap(x - C27[i][0], L->nx);
-        const int sy = wrap(y - C27[i][1], L->ny);
-        const int sz = wrap(z - C27[i][2], L->nz);
+        const int sx = wrap(x - cv[i][0], L->nx);
+        const int sy = wrap(y - cv[i][1], L->ny);
+        const int sz = wrap(z - cv[i][2], L->nz);
         const int64_t s = cell(L, sx, sy, sz);
         if (flags[s] & OFLAG_SOLID) {
             double v = f[(int64_t)opposite(i) * N + n];
             if (flags[s] & OFLAG_MOVING) {
-                const double cu = C27[i][0] * L->wall_u[0] + C27[i][1] * L->wall_u[1]
-                                + C27[i][2] * L->wall_u[2];
+                const double cu = cv[i][0] * L->wall_u[0] + cv[i][1] * L->wall_u[1]
+                                + cv[i][2] * L->wall_u[2];
                 v += 6.0 * weight(L->q, i) * 1.0 * cu;
             }
             fi[i] = v;
@@ -345,13 +388,14 @@ static void pull(const oracle_lattice *L, const double *f, const uint8_t *flags,
  * READING for the Guo force (only cited): u = (sum_i c_i f_i + F/2) / rho. */
 static void fields(const oracle_lattice *L, const double *fi, double *rho_out, double *u_out)
 {
+    const int (*cv)[3] = velocities(L->q);
     double rho = fi[0];
     for (int i = 1; i < L->q; i++) rho += fi[i];
     if (L->shifted) rho += 1.0;
     for (int a = 0; a < 3; a++) {
         double j = 0.0;
         for (int i = 1; i < L->q; i += 2) {
-            const int c = C27[i][a];
+            const int c = cv[i][a];
             if (c > 0) { j += fi[i]; j -= fi[i + 1]; }
             else if (c < 0) { j += fi[i + 1]; j -= fi[i]; }
         }
@@ -368,8 +412,9 @@ static void fields(const oracle_lattice *L, const double *fi, double *rho_out, d
 static void guo_parts(const oracle_lattice *L, int i, const double *u, double *sym, double *anti)
 {
     const double *F = L->force;
-    const double cF = C27[i][0] * F[0] + C27[i][1] * F[1] + C27[i][2] * F[2];
-    const double cu = C27[i][0] * u[0] + C27[i][1] * u[1] + C27[i][2] * u[2];
+    const int (*cv)[3] = velocities(L->q);
+    const double cF = cv[i][0] * F[0] + cv[i][1] * F[1] + cv[i][2] * F[2];
+    const double cu = cv[i][0] * u[0] + cv[i][1] * u[1] + cv[i][2] * u[2];
     const double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
     const double w = weight(L->q, i);
     *sym = w * (9.0 * cu * cF - 3.0 * uF);
@@ -429,7 +474,7 @@ static void collide_cell(const oracle_lattice *L, const double *fi, double *fo)
  * of their fixed density and velocity and are not updated either. */
 int oracle_step(const oracle_lattice *L, const double *fin, double *fout, const uint8_t *flags)
 {
-    if (L->q != 19 && L->q != 27) return -1;
+    if (!valid_q(L->q)) return -1;
     const int64_t N = (int64_t)L->nx * L->ny * L->nz;
     if (L->storage >= OF_FP16) build_table(L->storage);   /* before the threads start */
 #ifdef _OPENMP
@@ -546,19 +591,20 @@ int oracle_diagnostics(const oracle_lattice *L, const double *f, const uint8_t *
                         ref2 += u_ref[a * N + n] * u_ref[a * N + n];
                     }
                 }
+                const int (*cv)[3] = velocities(L->q);
                 for (int i = 1; i < L->q; i++) {
-                    const int sx = wrap(x - C27[i][0], L->nx);
-                    const int sy = wrap(y - C27[i][1], L->ny);
-                    const int sz = wrap(z - C27[i][2], L->nz);
+                    const int sx = wrap(x - cv[i][0], L->nx);
+                    const int sy = wrap(y - cv[i][1], L->ny);
+                    const int sz = wrap(z - cv[i][2], L->nz);
                     const int64_t s = cell(L, sx, sy, sz);
                     if (!(flags[s] & OFLAG_SOLID)) continue;
                     const int o = opposite(i);
                     const double fo = f[(int64_t)o * N + n] + (L->shifted ? weight(L->q, o) : 0.0);
                     double mv = 0.0;
                     if (flags[s] & OFLAG_MOVING)
-                        mv = 6.0 * weight(L->q, i) * (C27[i][0] * L->wall_u[0] + C27[i][1] * L->wall_u[1]
-                                                      + C27[i][2] * L->wall_u[2]);
-                    for (int a = 0; a < 3; a++) force[a] += C27[o][a] * (2.0 * fo + mv);
+                        mv = 6.0 * weight(L->q, i) * (cv[i][0] * L->wall_u[0] + cv[i][1] * L->wall_u[1]
+                                                      + cv[i][2] * L->wall_u[2]);
+                    for (int a = 0; a < 3; a++) force[a] += cv[o][a] * (2.0 * fo + mv);
                 }
             }
     out[0] = mass;

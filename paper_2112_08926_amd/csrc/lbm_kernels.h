@@ -37,6 +37,10 @@ namespace lbm {
 // (+00 -00, 0+0 0-0, 00+ 00-, ++0 --0, +0+ -0-, 0++ 0--, +-0 -+0, +0- -0+,
 // 0+- 0-+); weights 1/3, 1/18, 1/36.  D3Q27 appends the corner pairs
 // (+++ ---, ++- --+, +-+ -+-, -++ +--); weights 8/27, 2/27, 1/54, 1/216.
+// D2Q9 (Table 1; the paper's Taylor-Green runs): rest, +x -x, +y -y,
+// ++ --, +- -+; weights 4/9, 1/9, 1/36.  D3Q15 (Table 1): rest, the six
+// faces as in D3Q19, the corner pairs as in D3Q27; weights 2/9, 1/9, 1/72.
+// Every set: direction 0 at rest, directions 2k-1 and 2k opposite.
 template <int Q> struct VelSet;
 
 struct VelSetTables {
@@ -59,6 +63,26 @@ template <> struct VelSet<27> : VelSetTables {
     static constexpr int Q = 27;
     __host__ __device__ static constexpr double w(int i) {
         return i == 0 ? 8.0 / 27.0 : (i < 7 ? 2.0 / 27.0 : (i < 19 ? 1.0 / 54.0 : 1.0 / 216.0));
+    }
+};
+template <> struct VelSet<9> {
+    static constexpr int Q = 9;
+    static constexpr int c[9][3] = {
+        { 0, 0, 0}, { 1, 0, 0}, {-1, 0, 0}, { 0, 1, 0}, { 0,-1, 0},
+        { 1, 1, 0}, {-1,-1, 0}, { 1,-1, 0}, {-1, 1, 0}};
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+};
+template <> struct VelSet<15> {
+    static constexpr int Q = 15;
+    static constexpr int c[15][3] = {
+        { 0, 0, 0},
+        { 1, 0, 0}, {-1, 0, 0}, { 0, 1, 0}, { 0,-1, 0}, { 0, 0, 1}, { 0, 0,-1},
+        { 1, 1, 1}, {-1,-1,-1}, { 1, 1,-1}, {-1,-1, 1}, { 1,-1, 1}, {-1, 1,-1},
+        {-1, 1, 1}, { 1,-1,-1}};
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 2.0 / 9.0 : (i < 7 ? 1.0 / 9.0 : 1.0 / 72.0);
     }
 };
 
@@ -707,7 +731,7 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
 
     // ---- load the source row segments
     for (uint32_t i = wave; i < (uint32_t)Q; i += nwaves) {
-        const int cx = VelSetTables::c[i][0], cy = VelSetTables::c[i][1], cz = VelSetTables::c[i][2];
+        const int cx = VelSet<Q>::c[i][0], cy = VelSet<Q>::c[i][1], cz = VelSet<Q>::c[i][2];
         const uint32_t sy = wrap_add(y, -cy, ny), sz = wrap_add(z, -cz, nz);
         const T* rp = src + (size_t)i * plane + (sy + sz * ny) * nx + x0;
         T* lp = s_ddf + i * RS + OFF;
@@ -1107,33 +1131,41 @@ struct FormatLaunchers {
                            s.lats, s.tiles, s.ntiles, s.parity, s.enc);
         return hipGetLastError();
     }
+    // several cells per lane and the LDS-staged kernel are built for D3Q19
+    // and D3Q27; the other sets run one cell per lane
+    static constexpr bool kWide(int Q) { return Q == 19 || Q == 27; }
+
     template <int Q, class A, int COLL>
     static hipError_t single_qac(const StepLaunch& s, const LatDev& L) {
-        if (s.staged) {
-            if (s.cpl == 1) return staged_single_k<Q, A, COLL, 1>(s, L);
-            if (s.cpl == 2) return staged_single_k<Q, A, COLL, 2>(s, L);
-            return hipErrorInvalidValue;
+        if (s.cpl == 1 && !s.staged) return single_cpl<Q, A, COLL, 1>(s, L);
+        if constexpr (kWide(Q)) {
+            if (s.staged) {
+                if (s.cpl == 1) return staged_single_k<Q, A, COLL, 1>(s, L);
+                if (s.cpl == 2) return staged_single_k<Q, A, COLL, 2>(s, L);
+                return hipErrorInvalidValue;
+            }
+            if constexpr (kMaxCpl >= 2)
+                if (s.cpl == 2) return single_cpl<Q, A, COLL, 2>(s, L);
+            if constexpr (kMaxCpl >= 4)
+                if (s.cpl == 4) return single_cpl<Q, A, COLL, 4>(s, L);
         }
-        if (s.cpl == 1) return single_cpl<Q, A, COLL, 1>(s, L);
-        if constexpr (kMaxCpl >= 2)
-            if (s.cpl == 2) return single_cpl<Q, A, COLL, 2>(s, L);
-        if constexpr (kMaxCpl >= 4)
-            if (s.cpl == 4) return single_cpl<Q, A, COLL, 4>(s, L);
         return hipErrorInvalidValue;
     }
     template <int Q, class A, int COLL>
     static hipError_t batched_qac(const StepLaunch& s) {
         if (s.dense) return (s.cpl == 1 && !s.staged) ? dense_k<Q, A, COLL>(s) : hipErrorInvalidValue;
-        if (s.staged) {
-            if (s.cpl == 1) return staged_batched_k<Q, A, COLL, 1>(s);
-            if (s.cpl == 2) return staged_batched_k<Q, A, COLL, 2>(s);
-            return hipErrorInvalidValue;
+        if (s.cpl == 1 && !s.staged) return batched_cpl<Q, A, COLL, 1>(s);
+        if constexpr (kWide(Q)) {
+            if (s.staged) {
+                if (s.cpl == 1) return staged_batched_k<Q, A, COLL, 1>(s);
+                if (s.cpl == 2) return staged_batched_k<Q, A, COLL, 2>(s);
+                return hipErrorInvalidValue;
+            }
+            if constexpr (kMaxCpl >= 2)
+                if (s.cpl == 2) return batched_cpl<Q, A, COLL, 2>(s);
+            if constexpr (kMaxCpl >= 4)
+                if (s.cpl == 4) return batched_cpl<Q, A, COLL, 4>(s);
         }
-        if (s.cpl == 1) return batched_cpl<Q, A, COLL, 1>(s);
-        if constexpr (kMaxCpl >= 2)
-            if (s.cpl == 2) return batched_cpl<Q, A, COLL, 2>(s);
-        if constexpr (kMaxCpl >= 4)
-            if (s.cpl == 4) return batched_cpl<Q, A, COLL, 4>(s);
         return hipErrorInvalidValue;
     }
 };

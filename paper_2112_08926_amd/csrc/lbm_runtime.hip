@@ -293,7 +293,9 @@ static void fill_dev(Lattice& L, int arith) {
 }
 
 static lbm_status check_params(const lbm_params& p, int k) {
-    if (p.q != 19 && p.q != 27) return fail(LBM_EINVAL, "lattice %d: q must be 19 or 27", k);
+    if (p.q != 9 && p.q != 15 && p.q != 19 && p.q != 27)
+        return fail(LBM_EINVAL, "lattice %d: q must be 9 (D2Q9), 15, 19 or 27", k);
+    if (p.q == 9 && p.nz != 1) return fail(LBM_EINVAL, "lattice %d: D2Q9 needs nz = 1", k);
     if (p.collision != LBM_SRT && p.collision != LBM_TRT) return fail(LBM_EINVAL, "lattice %d: unknown collision", k);
     if (p.storage < LBM_FP64 || p.storage > LBM_P16_2C) return fail(LBM_EINVAL, "lattice %d: unknown storage", k);
     if (p.arith != LBM_ARITH_FP32 && p.arith != LBM_ARITH_FP64) return fail(LBM_EINVAL, "lattice %d: unknown arith", k);
@@ -565,12 +567,12 @@ extern "C" lbm_status lbm_set_boundaries(lbm_handle* h, int32_t k, const uint8_t
     hipError_t e = hipMemcpyAsync(d_raw, fl.data(), L.N, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
         const dim3 grid((unsigned)((L.N + 255) / 256));
-        if (h->q == 19)
-            hipLaunchKernelGGL(k_mark_near<19>, grid, dim3(256), 0, h->stream, d_raw, L.flags, L.wall_mask, L.dev.nx,
-                               L.dev.ny, L.dev.nz);
-        else
-            hipLaunchKernelGGL(k_mark_near<27>, grid, dim3(256), 0, h->stream, d_raw, L.flags, L.wall_mask, L.dev.nx,
-                               L.dev.ny, L.dev.nz);
+        switch (h->q) {
+#define LBM_MARK(QQ) case QQ: hipLaunchKernelGGL(k_mark_near<QQ>, grid, dim3(256), 0, h->stream, d_raw, L.flags, \
+                                                 L.wall_mask, L.dev.nx, L.dev.ny, L.dev.nz); break;
+        LBM_MARK(9) LBM_MARK(15) LBM_MARK(19) LBM_MARK(27)
+#undef LBM_MARK
+        }
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // fl is a local buffer
@@ -712,6 +714,8 @@ static lbm_status check_launch(lbm_handle* h, const lbm_launch& c) {
     if (c.staged != 0 && c.staged != 1) return fail(LBM_EINVAL, "staged must be 0 or 1");
     if (c.mode == LBM_LAUNCH_DENSE && (c.staged || c.cells_per_lane != 1))
         return fail(LBM_EINVAL, "cell-contiguous tiles take one cell per lane and no staging");
+    if (h->q != 19 && h->q != 27 && (c.staged || c.cells_per_lane != 1))
+        return fail(LBM_EUNSUPPORTED, "several cells per lane and the staged kernel are built for D3Q19 and D3Q27");
     if (c.staged) {
         if (c.cells_per_lane != 1 && c.cells_per_lane != 2)
             return fail(LBM_EINVAL, "the staged kernel takes 1 or 2 cells per thread");

@@ -47,7 +47,7 @@ def test_struct_layout_matches_header(tmp_path):
     assert got == expect
 
 
-@pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", 0.3), ("nx", 0), ("q", 15),
+@pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", 0.3), ("nx", 0), ("q", 13), ("q", 7), ("q", 9),
                                          ("storage", 9), ("unshifted", 2), ("nz", 70000)])
 def test_create_rejects_invalid_params_without_device(field, value):
     import paper_2112_08926_amd as lbm

@@ -378,3 +378,89 @@ def test_dense_tiles_bit_identical(lbm, orc, storage, q, collision):
             out[name] = g.get_ddf(0)
     for name in ("dense64", "dense512_pers", "dense128_graph"):
         assert np.array_equal(out["rows"], out[name]), name
+
+
+def _inputs_2d(nx, ny, seed, solid_frac=0.05):
+    """D2Q9 counterpart of one_step_inputs: random walls, a moving wall row
+    at y = ny-1, an EQ row at y = 0, random in-plane fields."""
+    N = nx * ny
+    rng = np.random.default_rng(seed)
+    flags = np.where(rng.random(N) < solid_frac, wl.SOLID, 0).astype(np.uint8)
+    f2 = flags.reshape(ny, nx)
+    f2[-1, :] = wl.SOLID | wl.MOVING
+    f2[0, :] = np.where(f2[0, :] & wl.SOLID, f2[0, :], wl.EQ)
+    rho, u = wl.random_fields(N, seed)
+    u[2] = 0.0
+    return flags, rho, u
+
+
+@pytest.mark.parametrize("q,collision", [(9, "srt"), (9, "trt"), (15, "srt"), (15, "trt")])
+@pytest.mark.parametrize("storage", FORMATS)
+def test_one_step_other_velocity_sets(lbm, orc, storage, q, collision):
+    """D2Q9 and D3Q15 (Table 1): one GPU step from the same stored DDFs as
+    the reference, with walls, a moving wall, EQ cells and a body force, on
+    ragged rows (300 cells)."""
+    say("one-step", storage, q, collision)
+    if q == 9:
+        nx, ny, nz = 300, 11, 1
+        flags, rho, u = _inputs_2d(nx, ny, seed=17)
+        force, wall_u, eq_u = (1e-4, -2e-5, 0.0), (0.08, 0.0, 0.0), (0.05, 0.0, 0.0)
+    else:
+        nx, ny, nz = 300, 6, 5
+        flags, rho, u = one_step_inputs(nx, ny, nz, q, seed=23)
+        force, wall_u, eq_u = (1e-4, -2e-5, 3e-5), (0.0, 0.08, 0.01), (0.05, 0.0, 0.0)
+    ref = orc.Lattice(nx, ny, nz, q=q, tau=0.56, collision=collision, storage=storage, force=force,
+                      wall_u=wall_u, flags=flags)
+    eq = (flags & wl.EQ) != 0
+    rho0, u0 = rho.copy(), u.copy()
+    rho0[eq] = 1.02
+    u0[:, eq] = np.array(eq_u)[:, None]
+    ref.init(rho0, u0)
+    noise = wl.random_noise(q, ref.N, seed=5) * (flags == 0)
+    ref.f = orc.store(storage, ref.f + noise)
+    codes = ref_codes(orc, storage, ref.f)
+    p = lbm.make_params(nx, ny, nz, q=q, collision=collision, storage=storage, arith=_arith(storage),
+                        tau=0.56, force=force, wall_u=wall_u, eq_rho=1.02, eq_u=eq_u)
+    with lbm.Lattices(p) as g:
+        g.set_boundaries(0, flags)
+        g.set_ddf(0, codes)
+        g.step(1)
+        out = g.get_ddf(0)
+        # cell-contiguous tiles give the same step
+        g.set_ddf(0, codes)
+        g.set_launch(mode=2, block=128)
+        g.step(1)
+        out_dense = g.get_ddf(0)
+    ref.step(1)
+    assert np.array_equal(out, out_dense)
+    same = assert_step_parity(orc, storage, out, ref.f, f"{storage} Q{q} {collision}")
+    say("  identical codes:", same)
+
+
+def test_d2q9_fp64_taylor_green_matches_reference(lbm, orc):
+    """The paper's Taylor-Green setup (D2Q9 SRT, Sec. 4.2) on a 64^2 box,
+    tau 0.6, u0 0.05, FP64, 500 steps: relative 1e-12 against the reference."""
+    n, tau, u0, steps = 64, 0.6, 0.05, 500
+    rho, u = wl.taylor_green_fields(n, n, 1, u0)
+    ref = orc.Lattice(n, n, 1, q=9, tau=tau).init(rho, u)
+    ref.step(steps)
+    rho_r, u_r = ref.moments()
+    p = lbm.make_params(n, n, 1, q=9, storage="fp64", arith="fp64", tau=tau)
+    with lbm.Lattices(p) as g:
+        g.set_rho_u(0, rho, u)
+        g.step(steps)
+        rho_g, u_g = g.get_rho_u(0)
+        d = g.diagnostics(0)
+    assert np.abs(u_g - u_r).max() <= 1e-12 * np.abs(u_r).max()
+    assert np.abs(rho_g - rho_r).max() <= 1e-12
+    assert d["kinetic_energy"] == pytest.approx(ref.diagnostics()["kinetic_energy"], rel=1e-11)
+
+
+def test_other_velocity_sets_rejected_where_not_built(lbm):
+    with pytest.raises(lbm.LbmError):
+        lbm.Lattices(lbm.make_params(16, 16, 2, q=9))            # D2Q9 needs nz = 1
+    with lbm.Lattices(lbm.make_params(32, 4, 4, q=15, storage="fp16s")) as g:
+        with pytest.raises(lbm.LbmError):
+            g.set_launch(cells_per_lane=2)
+        with pytest.raises(lbm.LbmError):
+            g.set_launch(staged=1)
