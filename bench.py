@@ -97,6 +97,45 @@ def measure_format(storage, n, steps, warmup):
             "launch": {k: cfg[k] for k in ("block", "cells_per_lane", "staged")}}
 
 
+def periodic_box(steps=50, warmup=5):
+    """The paper's performance workload (its Table 5): D3Q19 SRT on a periodic
+    256^3 box without boundaries, in the five arithmetic/storage columns the
+    paper reports (FP64/FP64, FP64/FP32, FP32/FP32, FP32/FP16S, FP32/FP16C);
+    the SRT/TRT/MRT triplet of its roofline (Sec. 5); and the other velocity
+    sets with FP32 and FP16S storage (D2Q9 on a 4096^2 box, D3Q15 and D3Q27
+    on 256^3).  Each configuration is autotuned first.  Bytes per cell are
+    the algorithmic 2 Q b + 1."""
+    import paper_2112_08926_amd as lbm
+    import lbm_workloads as wl
+    rows = []
+    cols = [(19, "srt", "fp64", "fp64"), (19, "srt", "fp64", "fp32"), (19, "srt", "fp32", "fp32"),
+            (19, "srt", "fp32", "fp16s"), (19, "srt", "fp32", "fp16c"),
+            (19, "trt", "fp32", "fp32"), (19, "trt", "fp32", "fp16s"), (19, "trt", "fp32", "fp16c"),
+            (19, "mrt", "fp32", "fp32"), (19, "mrt", "fp32", "fp16s"), (19, "mrt", "fp32", "fp16c"),
+            (9, "srt", "fp32", "fp32"), (9, "srt", "fp32", "fp16s"), (15, "srt", "fp32", "fp32"),
+            (15, "srt", "fp32", "fp16s"), (27, "srt", "fp32", "fp32"), (27, "srt", "fp32", "fp16s")]
+    for q, coll, arith, storage in cols:
+        nx, ny, nz = (4096, 4096, 1) if q == 9 else (256, 256, 256)
+        p = lbm.make_params(nx, ny, nz, q=q, collision=coll, storage=storage, arith=arith, tau=0.6)
+        g = lbm.Lattices(p)
+        try:
+            rho, u = wl.taylor_green_fields(nx, ny, nz, 0.05)
+            g.set_rho_u(0, rho, u)
+            cfg = g.autotune(2)
+            ms = time_steps(g, steps, warmup)
+        finally:
+            g.close()
+        N = nx * ny * nz
+        gbs = N * (2 * q * ddf_bytes(storage) + 1) / (ms * 1e-3) / 1e9
+        rows.append({"velset": f"D{2 if q == 9 else 3}Q{q}", "collision": coll, "arith": arith, "storage": storage,
+                     "cells": N, "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
+                     "achieved_GBps": round(gbs, 1), "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
+                     "launch": {k: cfg[k] for k in ("mode", "block", "cells_per_lane", "staged")}})
+        print(f"[bench] periodic {rows[-1]['velset']} {coll} {arith}/{storage}: {rows[-1]['mlups']:.0f} MLUPs/s, "
+              f"{gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    return rows
+
+
 def ensemble(storage="fp16s", count=256, steps=50, warmup=10):
     """The batched workload: `count` independent D3Q19 BGK lattices with sizes
     uniform in 32..96 per axis and tau uniform in [0.55, 1.0] (splitmix64,
@@ -236,6 +275,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-lattice ensemble")
+    ap.add_argument("--no-periodic", action="store_true",
+                    help="skip the periodic-box runs (the paper's performance workload, other velocity sets)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -268,6 +309,10 @@ def main():
     if not args.no_ensemble:
         print("[bench] ensemble of 256 lattices", file=sys.stderr, flush=True)
         ens = ensemble()
+    per = None
+    if not args.no_periodic:
+        print("[bench] periodic boxes", file=sys.stderr, flush=True)
+        per = periodic_box()
     cpu = None
     if not args.no_cpu:
         print("[bench] CPU reference timing", file=sys.stderr, flush=True)
@@ -300,6 +345,7 @@ def main():
                                   if "fp32" in results else None),
         "l2_vs_fp64": acc,
         "ensemble": ens,
+        "periodic_box": per,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line), flush=True)

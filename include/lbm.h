@@ -64,7 +64,14 @@ typedef enum {
  * D3Q7 does not conserve momentum (its c_s^2 is 1/4) and D3Q13 lacks the
  * fourth-order isotropy of the viscous stress.) */
 typedef enum { LBM_D2Q9 = 9, LBM_D3Q15 = 15, LBM_D3Q19 = 19, LBM_D3Q27 = 27 } lbm_velset;
-typedef enum { LBM_SRT = 0, LBM_TRT = 1 } lbm_collision;
+/* Collision operators (Sec. 2.1 names SRT, TRT and MRT; the paper defines
+ * none beyond its SRT listing).  TRT: the pairs' symmetric parts relax with
+ * 1/tau, the antisymmetric parts with the rate from trt_magic.  MRT (D3Q19
+ * only): the moment basis of d'Humieres et al. (2002) with rates 0 for rho
+ * and j, 1/tau for the five shear moments, 1.19 (e), 1.4 (eps, 3pi_xx,
+ * pi_ww), 1.2 (q) and 1.98 (m); the Guo source is added in moment space
+ * scaled by 1 - s/2. */
+typedef enum { LBM_SRT = 0, LBM_TRT = 1, LBM_MRT = 2 } lbm_collision;
 
 /* DDF storage formats (Sec. 3, Table 2).  Codes of the 16-bit formats:
  * FP16 IEEE binary16 (round to nearest even); FP16S binary16 of x*2^15;

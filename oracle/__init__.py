@@ -67,7 +67,8 @@ class _Lattice(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("shifted", ctypes.c_int32),
                 ("nthreads", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("omega_minus", ctypes.c_double),
-                ("force", ctypes.c_double * 3), ("wall_u", ctypes.c_double * 3)]
+                ("force", ctypes.c_double * 3), ("wall_u", ctypes.c_double * 3),
+                ("mrt_rates", ctypes.c_double * 19)]
 
 
 def _ptr(a, ctype):
@@ -140,6 +141,28 @@ def relaxation_rates(tau: float, trt_magic: float = 0.25):
     return wp, wm
 
 
+# The D3Q19 MRT moments in the order of the basis (rho, e, eps, j_x, q_x,
+# j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx, p_ww, pi_ww, p_xy, p_yz, p_xz, m_x, m_y,
+# m_z).  READING (the paper only names MRT): the rates d'Humieres et al.
+# (2002) use, with the shear moments at omega = 1/tau; the conserved moments
+# carry rate 0.
+MRT_SHEAR = (9, 11, 13, 14, 15)
+
+
+def mrt_rates(omega: float):
+    s = [0.0, 1.19, 1.4, 0.0, 1.2, 0.0, 1.2, 0.0, 1.2, omega, 1.4, omega, 1.4, omega, omega, omega,
+         1.98, 1.98, 1.98]
+    return np.array(s)
+
+
+def mrt_basis():
+    """(M[19, 19], |row|^2[19]) of the D3Q19 MRT moment basis."""
+    M = np.empty((19, 19))
+    n2 = np.empty(19)
+    lib().oracle_mrt_basis(_ptr(M, ctypes.c_double), _ptr(n2, ctypes.c_double))
+    return M, n2
+
+
 # --------------------------------------------------------------------------
 # lattice
 # --------------------------------------------------------------------------
@@ -149,7 +172,7 @@ class Lattice:
 
     def __init__(self, nx, ny, nz, q=19, tau=0.6, collision="srt", storage="fp64",
                  force=(0.0, 0.0, 0.0), wall_u=(0.0, 0.0, 0.0), trt_magic=0.25,
-                 shifted=True, flags=None, omega=None, omega_minus=None, nthreads=0):
+                 shifted=True, flags=None, omega=None, omega_minus=None, nthreads=0, rates=None):
         self.nx, self.ny, self.nz, self.q = int(nx), int(ny), int(nz), int(q)
         self.N = self.nx * self.ny * self.nz
         wp, wm = relaxation_rates(tau, trt_magic)
@@ -157,10 +180,12 @@ class Lattice:
             wp = omega
         if omega_minus is not None:
             wm = omega_minus
+        s = mrt_rates(wp) if rates is None else np.asarray(rates, dtype=np.float64)
         self.p = _Lattice(self.nx, self.ny, self.nz, self.q,
-                          {"srt": 0, "trt": 1}[collision], _fmt(storage), int(shifted),
+                          {"srt": 0, "trt": 1, "mrt": 2}[collision], _fmt(storage), int(shifted),
                           int(nthreads), wp, wm,
-                          (ctypes.c_double * 3)(*force), (ctypes.c_double * 3)(*wall_u))
+                          (ctypes.c_double * 3)(*force), (ctypes.c_double * 3)(*wall_u),
+                          (ctypes.c_double * 19)(*s))
         self.flags = (np.zeros(self.N, dtype=np.uint8) if flags is None
                       else np.ascontiguousarray(flags, dtype=np.uint8).reshape(self.N))
         self.f = np.zeros((self.q, self.N), dtype=np.float64)

@@ -334,7 +334,7 @@ enum { OFLAG_SOLID = 1, OFLAG_EQ = 2, OFLAG_MOVING = 4 };
 
 typedef struct {
     int32_t nx, ny, nz, q;
-    int32_t collision;     /* 0 SRT (BGK), 1 TRT */
+    int32_t collision;     /* 0 SRT (BGK), 1 TRT, 2 MRT (D3Q19) */
     int32_t storage;       /* emulated storage format of the new DDFs */
     int32_t shifted;       /* 1: the DDFs are f_i - w_i (Sec. 2.2) */
     int32_t nthreads;      /* OpenMP threads for the z loop (0: default) */
@@ -342,6 +342,7 @@ typedef struct {
     double omega_minus;    /* TRT antisymmetric rate (ignored for SRT) */
     double force[3];       /* Guo body force per volume */
     double wall_u[3];      /* velocity of MOVING wall cells (rho_w = 1) */
+    double mrt_rates[19];  /* MRT: relaxation rate of each moment (D3Q19) */
 } oracle_lattice;
 
 static inline int64_t cell(const oracle_lattice *L, int x, int y, int z)
@@ -421,6 +422,75 @@ static void guo_parts(const oracle_lattice *L, int i, const double *u, double *s
     *anti = w * 3.0 * cF;
 }
 
+/* READING for MRT (named in Sec. 2.1 and in the roofline of Sec. 5, not
+ * defined in the paper): the D3Q19 moment basis of d'Humieres et al. (2002),
+ * each moment a polynomial in c_i with c2 = |c_i|^2:
+ *   rho 1; e 19 c2 - 30; eps (21 c2^2 - 53 c2 + 24)/2;
+ *   j_a c_a and q_a (5 c2 - 9) c_a for a = x, y, z (interleaved j, q);
+ *   3p_xx 3 cx^2 - c2; 3pi_xx (3 c2 - 5)(3 cx^2 - c2);
+ *   p_ww cy^2 - cz^2; pi_ww (3 c2 - 5)(cy^2 - cz^2);
+ *   p_xy cx cy, p_yz cy cz, p_xz cx cz;
+ *   m_x (cy^2 - cz^2) cx, m_y (cz^2 - cx^2) cy, m_z (cx^2 - cy^2) cz.
+ * The rows are orthogonal, so M^-1 = M^T diag(1/|row|^2).  The collision
+ * relaxes the non-equilibrium moments M (f - f^eq) with the rates s_k (the
+ * equilibrium moments are those of the Sec. 2.2 equilibrium, M f^eq) and adds
+ * the Guo source in moment space scaled by (1 - s_k/2):
+ *   f' = f - M^-1 [ S M (f - f^eq) - (I - S/2) M S^F ].
+ * With every s_k equal to omega this is the SRT step.  Shifting drops out of
+ * f - f^eq. */
+static void mrt_basis(double M[19][19], double norm2[19])
+{
+    for (int i = 0; i < 19; i++) {
+        const double cx = C27[i][0], cy = C27[i][1], cz = C27[i][2];
+        const double c2 = cx * cx + cy * cy + cz * cz;
+        const double row[19] = {
+            1.0, 19.0 * c2 - 30.0, (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0,
+            cx, (5.0 * c2 - 9.0) * cx, cy, (5.0 * c2 - 9.0) * cy, cz, (5.0 * c2 - 9.0) * cz,
+            3.0 * cx * cx - c2, (3.0 * c2 - 5.0) * (3.0 * cx * cx - c2),
+            cy * cy - cz * cz, (3.0 * c2 - 5.0) * (cy * cy - cz * cz),
+            cx * cy, cy * cz, cx * cz,
+            (cy * cy - cz * cz) * cx, (cz * cz - cx * cx) * cy, (cx * cx - cy * cy) * cz};
+        for (int k = 0; k < 19; k++) M[k][i] = row[k];
+    }
+    for (int k = 0; k < 19; k++) {
+        norm2[k] = 0.0;
+        for (int i = 0; i < 19; i++) norm2[k] += M[k][i] * M[k][i];
+    }
+}
+
+void oracle_mrt_basis(double *M, double *norm2)
+{
+    double m[19][19];
+    mrt_basis(m, norm2);
+    for (int k = 0; k < 19; k++)
+        for (int i = 0; i < 19; i++) M[19 * k + i] = m[k][i];
+}
+
+static void collide_mrt(const oracle_lattice *L, const double *fi, const double *feq, const double *u,
+                        int forced, double *fo)
+{
+    double M[19][19], n2[19], r[19], src[19];
+    mrt_basis(M, n2);
+    for (int i = 0; i < 19; i++) {
+        double s = 0.0, an = 0.0;
+        if (forced) guo_parts(L, i, u, &s, &an);
+        src[i] = s + an;
+    }
+    for (int k = 0; k < 19; k++) {
+        double m = 0.0, g = 0.0;
+        for (int i = 0; i < 19; i++) {
+            m += M[k][i] * (fi[i] - feq[i]);
+            g += M[k][i] * src[i];
+        }
+        r[k] = L->mrt_rates[k] * m - (1.0 - 0.5 * L->mrt_rates[k]) * g;
+    }
+    for (int i = 0; i < 19; i++) {
+        double d = 0.0;
+        for (int k = 0; k < 19; k++) d += M[k][i] * r[k] / n2[k];
+        fo[i] = fi[i] - d;
+    }
+}
+
 static void collide_cell(const oracle_lattice *L, const double *fi, double *fo)
 {
     double rho, u[3], feq[27];
@@ -430,7 +500,9 @@ static void collide_cell(const oracle_lattice *L, const double *fi, double *fo)
     oracle_equilibrium(L->q, L->shifted, rho, u, feq);
     const int forced = (L->force[0] != 0.0 || L->force[1] != 0.0 || L->force[2] != 0.0);
     const double w = L->omega;
-    if (L->collision == 0) {
+    if (L->collision == 2) {
+        collide_mrt(L, fi, feq, u, forced, fo);
+    } else if (L->collision == 0) {
         /* SRT / BGK: f' = (1 - 1/tau) f + (1/tau) feq, as one FMA */
         for (int i = 0; i < L->q; i++) {
             double v = fma(1.0 - w, fi[i], w * feq[i]);
@@ -475,6 +547,7 @@ static void collide_cell(const oracle_lattice *L, const double *fi, double *fo)
 int oracle_step(const oracle_lattice *L, const double *fin, double *fout, const uint8_t *flags)
 {
     if (!valid_q(L->q)) return -1;
+    if (L->collision == 2 && L->q != 19) return -1;     /* the MRT basis is D3Q19's */
     const int64_t N = (int64_t)L->nx * L->ny * L->nz;
     if (L->storage >= OF_FP16) build_table(L->storage);   /* before the threads start */
 #ifdef _OPENMP

@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2, "fp16s": 3, "fp16c": 4,
            "p16_0s": 5, "p16_1s": 6, "p16_2c": 7}
-COLLISION = {"srt": 0, "trt": 1}
+COLLISION = {"srt": 0, "trt": 1, "mrt": 2}
 ARITH = {"fp32": 0, "fp64": 1}
 FLAG_SOLID, FLAG_EQ, FLAG_MOVING = 1, 2, 4
 LAUNCH_PER_LATTICE, LAUNCH_BATCHED = 0, 1

@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "lbm_codecs.h"
 #include "lbm_internal.h"
 
@@ -255,6 +257,124 @@ template <class A> __device__ __forceinline__ A fmaa(A a, A b, A c) {
     else return __builtin_fma(a, b, c);
 }
 
+// ------------------------------------------------------------ MRT (D3Q19)
+// Moment basis of d'Humieres et al. (2002), each row a polynomial in c_i
+// (c2 = |c_i|^2): rho 1; e 19 c2 - 30; eps (21 c2^2 - 53 c2 + 24)/2; j_a c_a
+// and q_a (5 c2 - 9) c_a interleaved for x, y, z; 3p_xx 3 cx^2 - c2;
+// 3pi_xx (3 c2 - 5)(3 cx^2 - c2); p_ww cy^2 - cz^2; pi_ww (3 c2 - 5)(cy^2 - cz^2);
+// p_xy, p_yz, p_xz; m_x (cy^2 - cz^2) cx, m_y (cz^2 - cx^2) cy,
+// m_z (cx^2 - cy^2) cz.  The rows are orthogonal: M^-1 = M^T diag(1/|row|^2).
+__host__ __device__ constexpr int mrt_m(int k, int i) {
+    const int cx = VelSet<19>::c[i][0], cy = VelSet<19>::c[i][1], cz = VelSet<19>::c[i][2];
+    const int c2 = cx * cx + cy * cy + cz * cz;
+    switch (k) {
+    case 0: return 1;
+    case 1: return 19 * c2 - 30;
+    case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+    case 3: return cx;
+    case 4: return (5 * c2 - 9) * cx;
+    case 5: return cy;
+    case 6: return (5 * c2 - 9) * cy;
+    case 7: return cz;
+    case 8: return (5 * c2 - 9) * cz;
+    case 9: return 3 * cx * cx - c2;
+    case 10: return (3 * c2 - 5) * (3 * cx * cx - c2);
+    case 11: return cy * cy - cz * cz;
+    case 12: return (3 * c2 - 5) * (cy * cy - cz * cz);
+    case 13: return cx * cy;
+    case 14: return cy * cz;
+    case 15: return cx * cz;
+    case 16: return (cy * cy - cz * cz) * cx;
+    case 17: return (cz * cz - cx * cx) * cy;
+    default: return (cx * cx - cy * cy) * cz;
+    }
+}
+__host__ __device__ constexpr int mrt_norm2(int k) {
+    int n = 0;
+    for (int i = 0; i < 19; i++) n += mrt_m(k, i) * mrt_m(k, i);
+    return n;
+}
+// Relaxation rate of moment k: 0 for the conserved rho and j, omega = 1/tau
+// for the shear moments (3p_xx, p_ww, p_xy, p_yz, p_xz), and the fixed rates
+// of d'Humieres et al. for the others.
+__host__ __device__ constexpr double mrt_rate_fixed(int k) {
+    switch (k) {
+    case 1: return 1.19;
+    case 2: case 10: case 12: return 1.4;
+    case 4: case 6: case 8: return 1.2;
+    case 16: case 17: case 18: return 1.98;
+    default: return 0.0;
+    }
+}
+__host__ __device__ constexpr bool mrt_shear(int k) { return k == 9 || k == 11 || k == 13 || k == 14 || k == 15; }
+__host__ __device__ constexpr bool mrt_conserved(int k) { return k == 0 || k == 3 || k == 5 || k == 7; }
+
+// The matrix products as fold expressions over compile-time indices, so each
+// coefficient is a constant and the zero ones vanish.
+template <class A, int K, int... I>
+__device__ __forceinline__ A mrt_row(const A (&v)[19], std::integer_sequence<int, I...>) {
+    A acc = (A)0;
+    ((acc = mrt_m(K, I) != 0 ? fmaa((A)mrt_m(K, I), v[I], acc) : acc), ...);
+    return acc;
+}
+template <class A, int I, int... K>
+__device__ __forceinline__ A mrt_col(const A (&r)[19], std::integer_sequence<int, K...>) {
+    A acc = (A)0;
+    ((acc = mrt_m(K, I) != 0 ? fmaa((A)mrt_m(K, I), r[K], acc) : acc), ...);
+    return acc;
+}
+template <class A, int K>
+__device__ __forceinline__ A mrt_relax_one(A w, bool forced, const A (&d)[19], const A (&src)[19]) {
+    constexpr auto idx = std::make_integer_sequence<int, 19>{};
+    const A sk = mrt_shear(K) ? w : (A)mrt_rate_fixed(K);
+    A rk = (A)0;
+    if constexpr (!mrt_conserved(K)) rk = sk * mrt_row<A, K>(d, idx);
+    if (forced) rk = fmaa(-((A)1 - (A)0.5 * sk), mrt_row<A, K>(src, idx), rk);
+    return rk * (A)(1.0 / mrt_norm2(K));
+}
+template <class A, int... K>
+__device__ __forceinline__ void mrt_relax(A w, bool forced, const A (&d)[19], const A (&src)[19], A (&r)[19],
+                                          std::integer_sequence<int, K...>) {
+    ((r[K] = mrt_relax_one<A, K>(w, forced, d, src)), ...);
+}
+template <class A, int... I>
+__device__ __forceinline__ void mrt_back(const A (&f)[19], const A (&r)[19], A (&fo)[19],
+                                         std::integer_sequence<int, I...>) {
+    constexpr auto idx = std::make_integer_sequence<int, 19>{};
+    ((fo[I] = f[I] - mrt_col<A, I>(r, idx)), ...);
+}
+
+// f' = f - M^-1 [S M (f - f^eq) - (I - S/2) M S^F] with the Guo source S^F;
+// values in units of 2^-E like the rest of the collision.
+template <class A, int E>
+__device__ __forceinline__ void collide_mrt(A w, A rho, A rhom1, A C, A u3x, A u3y, A u3z, A ux, A uy, A uz,
+                                            A Fx, A Fy, A Fz, A uF, bool forced, const A (&f)[19], A feq0,
+                                            A (&fo)[19]) {
+    constexpr double kSc = (double)(1u << E);
+    const A sc = (A)kSc;
+    A d[19], src[19];
+    d[0] = f[0] - feq0;
+    src[0] = sc * ((A)VelSet<19>::w(0) * ((A)(-3) * uF));
+#pragma unroll
+    for (int i = 1; i < 19; i += 2) {
+        const A wi = (A)(VelSet<19>::w(i) * kSc);
+        const A B = cdot_i<19, A>(i, u3x, u3y, u3z);
+        const A t = fmaa(B, B, C);
+        d[i] = f[i] - fmaa(wi * rho, fmaa((A)0.5, t, B), wi * rhom1);
+        d[i + 1] = f[i + 1] - fmaa(wi * rho, fmaa((A)0.5, t, -B), wi * rhom1);
+        const A wp = (A)VelSet<19>::w(i);
+        const A cF = cdot_i<19, A>(i, Fx, Fy, Fz);
+        const A cu = cdot_i<19, A>(i, ux, uy, uz);
+        const A sym = wp * ((A)9 * cu * cF - (A)3 * uF);
+        const A anti = wp * (A)3 * cF;
+        src[i] = sc * (sym + anti);
+        src[i + 1] = sc * (sym - anti);
+    }
+    A r[19];                                     // relaxed moments, divided by |row|^2
+    mrt_relax<A>(w, forced, d, src, r, std::make_integer_sequence<int, 19>{});
+    mrt_back<A>(f, r, fo, std::make_integer_sequence<int, 19>{});
+}
+
 // Computes the post-collision DDFs fo[] of one cell from the pulled f[].
 // f and fo are in units of 2^-E (E = the storage's raw exponent, see
 // Codec::load_raw): density is sum(f) 2^-E + 1 and every term that enters
@@ -308,7 +428,9 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
     const A w0 = (A)(VelSet<Q>::w(0) * kSc);
     const A feq0 = fmaa(w0 * rho, (A)0.5 * C, w0 * rhom1);
 
-    if (COLL == 0) {
+    if constexpr (COLL == 2) {
+        collide_mrt<A, E>(w, rho, rhom1, C, u3x, u3y, u3z, ux, uy, uz, Fx, Fy, Fz, uF, forced, f, feq0, fo);
+    } else if constexpr (COLL == 0) {
         const A omw = (A)1 - w;
         const A pre = ((A)1 - (A)0.5 * w) * sc;
         fo[0] = fmaa(omw, f[0], w * feq0);
@@ -333,6 +455,7 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
             }
         }
     } else {
+        static_assert(COLL == 1, "collision operator");
         const A hw = (A)0.5 * w, hwm = (A)0.5 * wm;
         const A prep = ((A)1 - hw) * sc, prem = ((A)1 - hwm) * sc;
         fo[0] = fmaa(-w, f[0] - feq0, f[0]);
@@ -1132,13 +1255,13 @@ struct FormatLaunchers {
         return hipGetLastError();
     }
     // several cells per lane and the LDS-staged kernel are built for D3Q19
-    // and D3Q27; the other sets run one cell per lane
+    // and D3Q27 with SRT and TRT; the other sets and MRT run one cell per lane
     static constexpr bool kWide(int Q) { return Q == 19 || Q == 27; }
 
     template <int Q, class A, int COLL>
     static hipError_t single_qac(const StepLaunch& s, const LatDev& L) {
         if (s.cpl == 1 && !s.staged) return single_cpl<Q, A, COLL, 1>(s, L);
-        if constexpr (kWide(Q)) {
+        if constexpr (kWide(Q) && COLL != 2) {
             if (s.staged) {
                 if (s.cpl == 1) return staged_single_k<Q, A, COLL, 1>(s, L);
                 if (s.cpl == 2) return staged_single_k<Q, A, COLL, 2>(s, L);
@@ -1155,7 +1278,7 @@ struct FormatLaunchers {
     static hipError_t batched_qac(const StepLaunch& s) {
         if (s.dense) return (s.cpl == 1 && !s.staged) ? dense_k<Q, A, COLL>(s) : hipErrorInvalidValue;
         if (s.cpl == 1 && !s.staged) return batched_cpl<Q, A, COLL, 1>(s);
-        if constexpr (kWide(Q)) {
+        if constexpr (kWide(Q) && COLL != 2) {
             if (s.staged) {
                 if (s.cpl == 1) return staged_batched_k<Q, A, COLL, 1>(s);
                 if (s.cpl == 2) return staged_batched_k<Q, A, COLL, 2>(s);

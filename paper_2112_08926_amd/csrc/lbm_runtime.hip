@@ -296,7 +296,10 @@ static lbm_status check_params(const lbm_params& p, int k) {
     if (p.q != 9 && p.q != 15 && p.q != 19 && p.q != 27)
         return fail(LBM_EINVAL, "lattice %d: q must be 9 (D2Q9), 15, 19 or 27", k);
     if (p.q == 9 && p.nz != 1) return fail(LBM_EINVAL, "lattice %d: D2Q9 needs nz = 1", k);
-    if (p.collision != LBM_SRT && p.collision != LBM_TRT) return fail(LBM_EINVAL, "lattice %d: unknown collision", k);
+    if (p.collision != LBM_SRT && p.collision != LBM_TRT && p.collision != LBM_MRT)
+        return fail(LBM_EINVAL, "lattice %d: unknown collision", k);
+    if (p.collision == LBM_MRT && p.q != 19)
+        return fail(LBM_EUNSUPPORTED, "lattice %d: MRT is built for D3Q19", k);
     if (p.storage < LBM_FP64 || p.storage > LBM_P16_2C) return fail(LBM_EINVAL, "lattice %d: unknown storage", k);
     if (p.arith != LBM_ARITH_FP32 && p.arith != LBM_ARITH_FP64) return fail(LBM_EINVAL, "lattice %d: unknown arith", k);
     if (p.unshifted != 0 && p.unshifted != 1) return fail(LBM_EINVAL, "lattice %d: unshifted must be 0 or 1", k);
@@ -714,8 +717,10 @@ static lbm_status check_launch(lbm_handle* h, const lbm_launch& c) {
     if (c.staged != 0 && c.staged != 1) return fail(LBM_EINVAL, "staged must be 0 or 1");
     if (c.mode == LBM_LAUNCH_DENSE && (c.staged || c.cells_per_lane != 1))
         return fail(LBM_EINVAL, "cell-contiguous tiles take one cell per lane and no staging");
-    if (h->q != 19 && h->q != 27 && (c.staged || c.cells_per_lane != 1))
+    if ((h->q != 19 && h->q != 27) && (c.staged || c.cells_per_lane != 1))
         return fail(LBM_EUNSUPPORTED, "several cells per lane and the staged kernel are built for D3Q19 and D3Q27");
+    if (h->collision == LBM_MRT && (c.staged || c.cells_per_lane != 1))
+        return fail(LBM_EUNSUPPORTED, "MRT runs one cell per lane without staging");
     if (c.staged) {
         if (c.cells_per_lane != 1 && c.cells_per_lane != 2)
             return fail(LBM_EINVAL, "the staged kernel takes 1 or 2 cells per thread");

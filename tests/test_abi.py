@@ -66,6 +66,9 @@ def test_create_rejects_unsupported_combinations_without_device():
     with pytest.raises(lbm.LbmError) as ei:
         lbm.lbm_create([lbm.make_params(8, 8, 8), lbm.make_params(8, 8, 8, q=27)])
     assert ei.value.code == -4
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create(lbm.make_params(8, 8, 8, q=27, collision="mrt"))
+    assert ei.value.code == -4
 
 
 def test_codec_entry_points_reject_bad_arguments_without_device():

@@ -345,3 +345,73 @@ def test_trt_rates_and_viscosity(orc):
     lat.step(steps)
     rate = -math.log(lat.diagnostics()["kinetic_energy"] / e0) / steps
     assert rate / (4 * nu * k * k) == pytest.approx(1.0, abs=1e-2)
+
+
+# ---------------------------------------------------------------- MRT (D3Q19)
+def test_mrt_basis_rows_are_the_polynomials_and_orthogonal(orc):
+    """Rows of the moment basis are the stated polynomials of c_i (spot
+    checks written out per direction class), mutually orthogonal, with the
+    conserved moments rho, j as rows 0, 3, 5, 7."""
+    M, n2 = orc.mrt_basis()
+    c, _, _ = orc.velset(19)
+    cf = c.astype(float)
+    assert np.array_equal(M[0], np.ones(19))
+    assert np.array_equal(M[3], cf[:, 0]) and np.array_equal(M[5], cf[:, 1]) and np.array_equal(M[7], cf[:, 2])
+    # e: rest -30, faces -11, edges 8; eps: rest 12, faces -4, edges 1
+    assert M[1, 0] == -30 and M[1, 1] == -11 and M[1, 7] == 8
+    assert M[2, 0] == 12 and M[2, 1] == -4 and M[2, 7] == 1
+    # q_x: faces -4 c_x, edges c_x
+    assert M[4, 1] == -4 and M[4, 2] == 4 and M[4, 7] == 1 and M[4, 3] == 0
+    # m_x on the edge ++0 is (cy^2 - cz^2) cx = 1
+    assert M[16, 7] == 1 and M[16, 9] == -1
+    G = M @ M.T
+    assert np.array_equal(G, np.diag(np.diag(G)))
+    assert np.array_equal(np.diag(G), n2)
+
+
+def test_mrt_with_equal_rates_is_srt(orc):
+    """Every rate equal to omega: M^-1 (omega I) M = omega I, so MRT is the SRT
+    step (with the Guo force as well)."""
+    a = _random_periodic(orc, 19, "srt", 0.7, force=(1e-5, -2e-5, 3e-6))
+    b = orc.Lattice(a.nx, a.ny, a.nz, q=19, tau=0.7, collision="mrt", force=(1e-5, -2e-5, 3e-6),
+                    rates=np.full(19, 1 / 0.7))
+    b.f = a.f.copy()
+    a.step(3)
+    b.step(3)
+    assert np.allclose(a.f, b.f, atol=2e-16, rtol=0)
+
+
+@pytest.mark.parametrize("forced", [False, True])
+def test_mrt_conserves_mass_and_momentum(orc, forced):
+    F = np.array([2e-5, -1e-5, 3e-5]) if forced else np.zeros(3)
+    a = _random_periodic(orc, 19, "srt", 0.57)
+    lat = orc.Lattice(a.nx, a.ny, a.nz, q=19, tau=0.57, collision="mrt", force=F)
+    lat.f = a.f.copy()
+    c, _, _ = orc.velset(19)
+    m0 = lat.f.sum()
+    p0 = c.T.astype(float) @ lat.f.sum(axis=1)
+    lat.step(20)
+    assert lat.f.sum() == pytest.approx(m0, abs=1e-12)
+    assert np.allclose(c.T.astype(float) @ lat.f.sum(axis=1), p0 + 20 * lat.N * F, atol=1e-13)
+
+
+def test_mrt_shear_viscosity_from_taylor_green_decay(orc):
+    """The shear moments alone set the viscosity: the Taylor-Green energy
+    decays at 4 nu k^2 with nu = (1/s_nu - 1/2)/3, whatever the other rates
+    (two different sets of them give the same decay)."""
+    n, tau, u0, steps = 24, 0.7, 0.03, 600
+    nu = (tau - 0.5) / 3.0
+    k = 2 * math.pi / n
+    rho, u = wl.taylor_green_fields(n, n, 1, u0)
+    rates = []
+    for alt in (False, True):
+        r = orc.mrt_rates(1 / tau)
+        if alt:
+            r[[1, 2, 4, 6, 8, 10, 12, 16, 17, 18]] = [1.5, 1.1, 1.6, 1.6, 1.6, 1.2, 1.2, 1.7, 1.7, 1.7]
+        lat = orc.Lattice(n, n, 1, q=19, tau=tau, collision="mrt", rates=r).init(rho, u)
+        e0 = lat.diagnostics()["kinetic_energy"]
+        lat.step(steps)
+        rate = -math.log(lat.diagnostics()["kinetic_energy"] / e0) / steps
+        rates.append(rate)
+        assert rate / (4 * nu * k * k) == pytest.approx(1.0, abs=1e-2)
+    assert rates[0] == pytest.approx(rates[1], rel=2e-3)
