@@ -192,8 +192,9 @@ lbm_status lbm_get_rho_u(lbm_handle* h, int32_t lattice, double* rho, double* u)
 
 /* Raw DDF codes of the current state: host buffer of q*N elements of the
  * storage type (double, float or uint16), direction-major [i*N + n].
- * set: copies in (any values; used for checkpoints and exact comparisons);
- * get: copies out and synchronises. */
+ * set: copies in, to both DDF buffers so that cells the step never writes
+ * (SOLID, EQ) hold the same codes in both (any values; used for checkpoints
+ * and exact comparisons); get: copies out.  Both synchronise. */
 lbm_status lbm_set_ddf(lbm_handle* h, int32_t lattice, const void* host);
 lbm_status lbm_get_ddf(lbm_handle* h, int32_t lattice, void* host);
 

@@ -638,9 +638,11 @@ extern "C" lbm_status lbm_set_ddf(lbm_handle* h, int32_t k, const void* host) {
     if (!host) return fail(LBM_EINVAL, "host buffer is NULL");
     Lattice& L = h->lats[k];
     const size_t b = ddf_bytes(h->storage);
-    for (int i = 0; i < h->q; i++)
-        HIP_TRY(hipMemcpyAsync((char*)L.f[h->parity] + (size_t)i * L.plane * b, (const char*)host + (size_t)i * L.N * b,
-                               L.N * b, hipMemcpyHostToDevice, h->stream));
+    // both buffers, so that the cells a step never writes (SOLID, EQ) agree
+    for (int buf = 0; buf < 2; buf++)
+        for (int i = 0; i < h->q; i++)
+            HIP_TRY(hipMemcpyAsync((char*)L.f[buf] + (size_t)i * L.plane * b, (const char*)host + (size_t)i * L.N * b,
+                                   L.N * b, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return LBM_OK;
 }

@@ -380,6 +380,19 @@ def test_dense_tiles_bit_identical(lbm, orc, storage, q, collision):
         assert np.array_equal(out["rows"], out[name]), name
 
 
+def _one_gpu_step(lbm, p, flags, codes, launch=None):
+    """One step on a fresh handle from the given stored DDFs.  (A fresh handle
+    each time: EQ cells are never written by the step, so the other buffer's
+    EQ cells hold what the initialisation put there.)"""
+    with lbm.Lattices(p) as g:
+        g.set_boundaries(0, flags)
+        if launch:
+            g.set_launch(**launch)
+        g.set_ddf(0, codes)
+        g.step(1)
+        return g.get_ddf(0)
+
+
 def _inputs_2d(nx, ny, seed, solid_frac=0.05):
     """D2Q9 counterpart of one_step_inputs: random walls, a moving wall row
     at y = ny-1, an EQ row at y = 0, random in-plane fields."""
@@ -421,16 +434,8 @@ def test_one_step_other_velocity_sets(lbm, orc, storage, q, collision):
     codes = ref_codes(orc, storage, ref.f)
     p = lbm.make_params(nx, ny, nz, q=q, collision=collision, storage=storage, arith=_arith(storage),
                         tau=0.56, force=force, wall_u=wall_u, eq_rho=1.02, eq_u=eq_u)
-    with lbm.Lattices(p) as g:
-        g.set_boundaries(0, flags)
-        g.set_ddf(0, codes)
-        g.step(1)
-        out = g.get_ddf(0)
-        # cell-contiguous tiles give the same step
-        g.set_ddf(0, codes)
-        g.set_launch(mode=2, block=128)
-        g.step(1)
-        out_dense = g.get_ddf(0)
+    out = _one_gpu_step(lbm, p, flags, codes)
+    out_dense = _one_gpu_step(lbm, p, flags, codes, dict(mode=2, block=128))   # cell-contiguous tiles
     ref.step(1)
     assert np.array_equal(out, out_dense)
     same = assert_step_parity(orc, storage, out, ref.f, f"{storage} Q{q} {collision}")
@@ -487,15 +492,8 @@ def test_one_step_mrt(lbm, orc, storage):
     codes = ref_codes(orc, storage, ref.f)
     p = lbm.make_params(nx, ny, nz, q=19, collision="mrt", storage=storage, arith=_arith(storage),
                         tau=0.56, force=force, wall_u=wall_u, eq_rho=1.02, eq_u=eq_u)
-    with lbm.Lattices(p) as g:
-        g.set_boundaries(0, flags)
-        g.set_ddf(0, codes)
-        g.step(1)
-        out = g.get_ddf(0)
-        g.set_ddf(0, codes)
-        g.set_launch(mode=2, block=256)
-        g.step(1)
-        out_dense = g.get_ddf(0)
+    out = _one_gpu_step(lbm, p, flags, codes)
+    out_dense = _one_gpu_step(lbm, p, flags, codes, dict(mode=2, block=256))
     ref.step(1)
     assert np.array_equal(out, out_dense)
     same = assert_step_parity(orc, storage, out, ref.f, f"{storage} MRT")
