@@ -54,7 +54,9 @@ def gpu_errors(lbm):
         ux = u[0].reshape(NY, NY, NX)
         slice_spread = float(np.abs(ux - ux[:, :, :1]).max())
         errs[fmt] = (d["l2_error"], d["u_max"], slice_spread)
-        say("  E=%.4e umax=%.4e slice spread %.2e" % errs[fmt])
+        if fmt in ("fp64", "fp32"):
+            errs[fmt + "_u"] = u
+        say("  E=%.4e umax=%.4e slice spread %.2e" % errs[fmt][:3])
     return errs
 
 
@@ -92,10 +94,16 @@ def test_p16_0s_stalls_like_reference(gpu_errors):
 
 
 @pytest.mark.parametrize("fmt", ["fp32", "fp16s", "fp16c"])
-def test_without_ddf_shifting(lbm, fmt):
-    """Sec. 2.2 ablation: without DDF shifting FP32 is unaffected, while the
+def test_without_ddf_shifting(lbm, gpu_errors, fmt):
+    """Sec. 2.2 ablation (Sec. 4.1: without shifting the 16-bit formats become
+    unfeasible, and FP32 benefits from shifting at low velocities).  The
     16-bit formats cannot represent the small changes of f_i ~ w_i at this
-    velocity and the flow never develops (E ~ 1), as in the reference."""
+    velocity and the flow never develops (E ~ 1), as in the reference with
+    the storage emulated.  FP32 arithmetic without shifting loses digits in
+    rho = sum f_i ~ 1 and f_i - f_i^eq: its velocity field ends more than 3x
+    further from the FP64 run's than the shifted FP32 field.  (The reference's
+    fp32_unshifted line emulates only the storage, in FP64 arithmetic, and
+    shows the storage part of this alone: E 7.50e-3 vs 7.39e-3.)"""
     nu = (TAU - 0.5) / 3.0
     flags = wl.poiseuille_flags(NX, NY, NY, R)
     u_ref = wl.poiseuille_profile(NX, NY, NY, R, F, nu)
@@ -104,9 +112,14 @@ def test_without_ddf_shifting(lbm, fmt):
         g.set_boundaries(0, flags)
         g.step(STEPS)
         d = g.diagnostics(0, u_ref)
+        _, u = g.get_rho_u(0)
     e_ref = golden()[fmt + "_unshifted"][0]
     say("unshifted", fmt, "E=%.4e ref %.4e" % (d["l2_error"], e_ref))
     if fmt == "fp32":
-        assert d["l2_error"] == pytest.approx(e_ref, rel=1e-2)
+        u64 = gpu_errors["fp64_u"]
+        dev_plain = np.linalg.norm(u - u64) / np.linalg.norm(u64)
+        dev_shift = np.linalg.norm(gpu_errors["fp32_u"] - u64) / np.linalg.norm(u64)
+        say("  FP32 field vs FP64: shifted %.3e, unshifted %.3e" % (dev_shift, dev_plain))
+        assert dev_plain > 3 * dev_shift
     else:
         assert d["l2_error"] > 0.9 and e_ref > 0.9
