@@ -495,14 +495,17 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     make_rows(L, y, z, rc);
     const uint32_t n = rc.rows[4] + x;
     const uint8_t fl = ld_off(L.flags, n);
-    if (fl & (F_SOLID | F_EQ)) return;
     const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
     const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
     const T* __restrict__ src = (const T*)L.f[parity];
     T* __restrict__ dst = (T*)L.f[parity ^ 1];
 
+    // The DDF loads go out together with the flag load (every address is in
+    // the lattice whatever the flag), so a wavefront waits for memory once;
+    // wall and EQ cells then drop out before the collision.
     A f[Q], fo[Q];
     pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+    if (fl & (F_SOLID | F_EQ)) return;
     collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
     const size_t plane = L.plane;
 #pragma unroll
@@ -543,14 +546,14 @@ __device__ __forceinline__ void step_tile_dense(const LatDev& L, uint32_t x0, ui
     make_rows(L, y, z, rc);
     const uint32_t n = rc.rows[4] + x;
     const uint8_t fl = ld_off(L.flags, n);
-    if (fl & (F_SOLID | F_EQ)) return;
     const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
     const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
     const T* __restrict__ src = (const T*)L.f[parity];
     T* __restrict__ dst = (T*)L.f[parity ^ 1];
 
     A f[Q], fo[Q];
-    pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+    pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);   // loads with the flag's
+    if (fl & (F_SOLID | F_EQ)) return;
     collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
     const size_t plane = L.plane;
 #pragma unroll
@@ -945,9 +948,8 @@ __global__ void __launch_bounds__(512) k_step_staged_single(LatDev L, int parity
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
-    const uint32_t b = blockIdx.x;
-    const uint32_t seg = b % segs, row = b / segs;
-    staged_tile<Q, F, A, COLL, K>(L, seg * blockDim.x * K, row % L.ny, row / L.ny, parity, tab, lds_dyn);
+    // grid (segments, ny, nz): no index division
+    staged_tile<Q, F, A, COLL, K>(L, blockIdx.x * blockDim.x * K, blockIdx.y, blockIdx.z, parity, tab, lds_dyn);
 }
 
 template <int Q, int F, class A, int COLL, int K>
@@ -975,10 +977,8 @@ __global__ void __launch_bounds__(512) k_step_single(LatDev L, int parity, uint3
                                                      const EncEntry* __restrict__ enc) {
     __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
-    const uint32_t b = blockIdx.x;
-    const uint32_t seg = b % segs, row = b / segs;
-    const uint32_t y = row % L.ny, z = row / L.ny;
-    run_tile<Q, F, A, COLL, CPL>(L, seg * blockDim.x * CPL, y, z, parity, tab);
+    // grid (segments, ny, nz): no index division
+    run_tile<Q, F, A, COLL, CPL>(L, blockIdx.x * blockDim.x * CPL, blockIdx.y, blockIdx.z, parity, tab);
 }
 
 // Ensemble: workgroups walk the tile table (one tile each, or a persistent
@@ -1218,8 +1218,7 @@ struct FormatLaunchers {
     static hipError_t single_cpl(const StepLaunch& s, const LatDev& L) {
         const uint32_t per_wg = (uint32_t)s.block * CPL;
         const uint32_t segs = (L.nx + per_wg - 1) / per_wg;
-        const uint32_t grid = segs * L.ny * L.nz;
-        hipLaunchKernelGGL((k_step_single<Q, F, A, COLL, CPL>), dim3(grid), dim3(s.block), 0, s.stream, L,
+        hipLaunchKernelGGL((k_step_single<Q, F, A, COLL, CPL>), dim3(segs, L.ny, L.nz), dim3(s.block), 0, s.stream, L,
                            s.parity, segs, s.enc);
         return hipGetLastError();
     }
@@ -1240,10 +1239,9 @@ struct FormatLaunchers {
         using T = typename Codec<F>::T;
         const uint32_t per_wg = (uint32_t)s.block * K;
         const uint32_t segs = (L.nx + per_wg - 1) / per_wg;
-        const uint32_t grid = segs * L.ny * L.nz;
         const size_t lds = staged_lds<Q, T>(s.block, K);
-        hipLaunchKernelGGL((k_step_staged_single<Q, F, A, COLL, K>), dim3(grid), dim3(s.block), lds, s.stream, L,
-                           s.parity, segs, s.enc);
+        hipLaunchKernelGGL((k_step_staged_single<Q, F, A, COLL, K>), dim3(segs, L.ny, L.nz), dim3(s.block), lds,
+                           s.stream, L, s.parity, segs, s.enc);
         return hipGetLastError();
     }
     template <int Q, class A, int COLL, int K>
