@@ -484,6 +484,31 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
     }
 }
 
+// What a wall or EQ cell keeps: zero DDFs, or the lattice's equilibrium
+// codes.  The step writes them back unchanged, so that every wavefront
+// writes whole rows: a store that leaves holes in a cache line makes the
+// memory side read the line to merge it, which at a wall in every row cost
+// ~15 % of the 512^3 cavity's step.
+template <int Q, int F>
+__device__ __forceinline__ typename Codec<F>::T special_code(const LatDev& L, uint32_t fl, int i) {
+    using T = typename Codec<F>::T;
+    return (fl & F_EQ) ? ld_off((const T*)L.eq_codes, (uint32_t)i) : (T)0;
+}
+// The code cell (flags fl) stores for direction i: the collision's, or what
+// a wall or EQ cell keeps.  The EQ table is read only by wavefronts that
+// hold an EQ cell (any_eq), so other wavefronts issue no extra loads.
+template <int Q, int F>
+__device__ __forceinline__ typename Codec<F>::T out_code(const LatDev& L, uint32_t fl, bool any_eq, int i,
+                                                         typename Codec<F>::T code) {
+    using T = typename Codec<F>::T;
+    if (fl & F_SOLID) code = (T)0;
+    if (any_eq) {
+        const T e = ld_off((const T*)L.eq_codes, (uint32_t)i);
+        if (fl & F_EQ) code = e;
+    }
+    return code;
+}
+
 // ------------------------------------------------------------ one tile of the step
 template <int Q, int F, class A, int COLL>
 __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z,
@@ -501,17 +526,17 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     T* __restrict__ dst = (T*)L.f[parity ^ 1];
 
     // The DDF loads go out together with the flag load (every address is in
-    // the lattice whatever the flag), so a wavefront waits for memory once;
-    // wall and EQ cells then drop out before the collision.
+    // the lattice whatever the flag), so a wavefront waits for memory once.
     A f[Q], fo[Q];
     pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
-    if (fl & (F_SOLID | F_EQ)) return;
-    collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
+    const bool special = (fl & (F_SOLID | F_EQ)) != 0;
+    if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
+    const bool any_eq = __any((fl & F_EQ) != 0);
     const size_t plane = L.plane;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         T* p = dst + ((size_t)i * plane + rc.rows[4]);
-        st_off(p, x, Codec<F>::template store_raw<A>(fo[i], tab));
+        st_off(p, x, out_code<Q, F>(L, fl, any_eq, i, Codec<F>::template store_raw<A>(fo[i], tab)));
     }
 }
 
@@ -553,11 +578,13 @@ __device__ __forceinline__ void step_tile_dense(const LatDev& L, uint32_t x0, ui
 
     A f[Q], fo[Q];
     pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);   // loads with the flag's
-    if (fl & (F_SOLID | F_EQ)) return;
-    collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
+    const bool special = (fl & (F_SOLID | F_EQ)) != 0;
+    if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
+    const bool any_eq = __any((fl & F_EQ) != 0);
     const size_t plane = L.plane;
 #pragma unroll
-    for (int i = 0; i < Q; i++) st_off(dst + (size_t)i * plane, n, Codec<F>::template store_raw<A>(fo[i], tab));
+    for (int i = 0; i < Q; i++)
+        st_off(dst + (size_t)i * plane, n, out_code<Q, F>(L, fl, any_eq, i, Codec<F>::template store_raw<A>(fo[i], tab)));
 }
 
 // ------------------------------------------------------------ several cells per lane
@@ -640,6 +667,19 @@ __device__ __forceinline__ void vset(RowVec<T, CPL>& r, int k, T v) {
     } else {
         r.w[2 * k] = (uint32_t)b;
         r.w[2 * k + 1] = (uint32_t)(b >> 32);
+    }
+}
+
+// Replaces element k, keeping the others (vset may clear the odd neighbour
+// of an even 16-bit element).
+template <class T, int CPL>
+__device__ __forceinline__ void vreplace(RowVec<T, CPL>& r, int k, T v) {
+    if constexpr (sizeof(T) == 2) {
+        const uint32_t b = (uint32_t)(uint16_t)v;
+        if (k & 1) r.w[k >> 1] = (r.w[k >> 1] & 0xFFFFu) | (b << 16);
+        else r.w[k >> 1] = (r.w[k >> 1] & 0xFFFF0000u) | b;
+    } else {
+        vset<T, CPL>(r, k, v);
     }
 }
 
@@ -791,18 +831,17 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
         for (int i = 0; i < Q; i++) vset<T, CPL>(out[i], k, Codec<F>::template store_raw<A>(fo[i], tab));
     }
     if (__any(any_special)) {
-        // wall and equilibrium cells keep their DDFs: element-wise stores
+        // wall and equilibrium cells write back what they keep (whole rows)
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            T* p = dst + ((size_t)i * plane + row + x);
+        for (int k = 0; k < CPL; k++) {
+            const uint32_t fk = (fl4 >> (8 * k)) & 0xFF;
 #pragma unroll
-            for (int k = 0; k < CPL; k++)
-                if (!special[k]) *(LBM_GLOBAL T*)(p + k) = velem<T, CPL>(out[i], k);
+            for (int i = 0; i < Q; i++)
+                if (special[k]) vreplace<T, CPL>(out[i], k, special_code<Q, F>(L, fk, i));
         }
-    } else {
-#pragma unroll
-        for (int i = 0; i < Q; i++) vstore<T, CPL>(dst + ((size_t)i * plane + row + x), out[i]);
     }
+#pragma unroll
+    for (int i = 0; i < Q; i++) vstore<T, CPL>(dst + ((size_t)i * plane + row + x), out[i]);
 }
 
 template <int F>
@@ -948,8 +987,8 @@ __global__ void __launch_bounds__(512) k_step_staged_single(LatDev L, int parity
     extern __shared__ __align__(16) char lds_dyn[];
     __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
-    // grid (segments, ny, nz): no index division
-    staged_tile<Q, F, A, COLL, K>(L, blockIdx.x * blockDim.x * K, blockIdx.y, blockIdx.z, parity, tab, lds_dyn);
+    // grid (ny, segments, nz), as for the unstaged kernel
+    staged_tile<Q, F, A, COLL, K>(L, blockIdx.y * blockDim.x * K, blockIdx.x, blockIdx.z, parity, tab, lds_dyn);
 }
 
 template <int Q, int F, class A, int COLL, int K>
@@ -977,8 +1016,11 @@ __global__ void __launch_bounds__(512) k_step_single(LatDev L, int parity, uint3
                                                      const EncEntry* __restrict__ enc) {
     __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
-    // grid (segments, ny, nz): no index division
-    run_tile<Q, F, A, COLL, CPL>(L, blockIdx.x * blockDim.x * CPL, blockIdx.y, blockIdx.z, parity, tab);
+    // grid (ny, segments, nz): no index division, and the segments of one row
+    // are ny workgroups apart, which for ny a multiple of 8 puts them on the
+    // same XCD (workgroups go round-robin to the 8 XCDs), so the cache lines
+    // their +-x neighbours share are fetched into one L2 only
+    run_tile<Q, F, A, COLL, CPL>(L, blockIdx.y * blockDim.x * CPL, blockIdx.x, blockIdx.z, parity, tab);
 }
 
 // Ensemble: workgroups walk the tile table (one tile each, or a persistent
@@ -1218,7 +1260,7 @@ struct FormatLaunchers {
     static hipError_t single_cpl(const StepLaunch& s, const LatDev& L) {
         const uint32_t per_wg = (uint32_t)s.block * CPL;
         const uint32_t segs = (L.nx + per_wg - 1) / per_wg;
-        hipLaunchKernelGGL((k_step_single<Q, F, A, COLL, CPL>), dim3(segs, L.ny, L.nz), dim3(s.block), 0, s.stream, L,
+        hipLaunchKernelGGL((k_step_single<Q, F, A, COLL, CPL>), dim3(L.ny, segs, L.nz), dim3(s.block), 0, s.stream, L,
                            s.parity, segs, s.enc);
         return hipGetLastError();
     }
@@ -1240,7 +1282,7 @@ struct FormatLaunchers {
         const uint32_t per_wg = (uint32_t)s.block * K;
         const uint32_t segs = (L.nx + per_wg - 1) / per_wg;
         const size_t lds = staged_lds<Q, T>(s.block, K);
-        hipLaunchKernelGGL((k_step_staged_single<Q, F, A, COLL, K>), dim3(segs, L.ny, L.nz), dim3(s.block), lds,
+        hipLaunchKernelGGL((k_step_staged_single<Q, F, A, COLL, K>), dim3(L.ny, segs, L.nz), dim3(s.block), lds,
                            s.stream, L, s.parity, segs, s.enc);
         return hipGetLastError();
     }
