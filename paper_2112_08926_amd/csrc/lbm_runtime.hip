@@ -216,6 +216,18 @@ struct Lattice {
     uint32_t* wall_mask = nullptr;
     void* eq_codes = nullptr;   // q codes of the EQ state
     LatDev dev{};
+    // host copy of the caller's flags (empty: no walls), for the tile tables:
+    // tiles of wall cells only need no work (their DDFs stay zero) and are
+    // left out; tiles with EQ cells are kept, so that every launch mode
+    // writes the same equilibrium codes there
+    std::vector<uint8_t> host_flags;
+    bool needs_step(size_t n0, size_t count) const {
+        if (host_flags.empty()) return true;
+        const size_t end = std::min(n0 + count, N);
+        for (size_t n = n0; n < end; n++)
+            if (!(host_flags[n] & LBM_FLAG_SOLID)) return true;
+        return false;
+    }
 };
 
 struct lbm_handle {
@@ -446,22 +458,27 @@ static lbm_status rebuild_tiles(lbm_handle* h) {
     std::vector<Tile> tiles;
     for (size_t k = 0; k < h->lats.size(); k++) {
         const lbm_params& p = h->lats[k].p;
+        const Lattice& L = h->lats[k];
         if (dense) {
             // T consecutive cells each, from the start cell's coordinates
-            const size_t N = h->lats[k].N, row = (size_t)p.nx, slab = row * p.ny;
+            const size_t N = L.N, row = (size_t)p.nx, slab = row * p.ny;
             for (size_t n0 = 0; n0 < N; n0 += T)
-                tiles.push_back(Tile{(uint16_t)k, (uint16_t)(n0 % row), (uint16_t)((n0 / row) % p.ny),
-                                     (uint16_t)(n0 / slab)});
+                if (L.needs_step(n0, T))
+                    tiles.push_back(Tile{(uint16_t)k, (uint16_t)(n0 % row), (uint16_t)((n0 / row) % p.ny),
+                                         (uint16_t)(n0 / slab)});
             continue;
         }
         for (int z = 0; z < p.nz; z++)
             for (int y = 0; y < p.ny; y++)
-                for (int x0 = 0; x0 < p.nx; x0 += T)
-                    tiles.push_back(Tile{(uint16_t)k, (uint16_t)x0, (uint16_t)y, (uint16_t)z});
+                for (int x0 = 0; x0 < p.nx; x0 += T) {
+                    const size_t n0 = (size_t)x0 + (size_t)p.nx * ((size_t)y + (size_t)p.ny * z);
+                    if (L.needs_step(n0, std::min<size_t>(T, p.nx - x0)))
+                        tiles.push_back(Tile{(uint16_t)k, (uint16_t)x0, (uint16_t)y, (uint16_t)z});
+                }
     }
     if (tiles.size() >= 0xFFFFFFFFull) return fail(LBM_EINVAL, "too many tiles");
     dev_free(h, h->d_tiles);
-    h->d_tiles = (Tile*)dev_alloc(h, sizeof(Tile) * tiles.size());
+    h->d_tiles = (Tile*)dev_alloc(h, sizeof(Tile) * std::max<size_t>(tiles.size(), 1));   // may be empty
     if (!h->d_tiles) return fail(LBM_ENOMEM, "tile table allocation failed");
     HIP_TRY(hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -495,7 +512,7 @@ static StepLaunch make_launch(lbm_handle* h, const lbm_launch& cfg, int parity) 
 // Enqueue one time step with the given configuration, reading buffer `parity`.
 static hipError_t enqueue_step(lbm_handle* h, const lbm_launch& cfg, int parity) {
     const StepLaunch s = make_launch(h, cfg, parity);
-    if (cfg.mode != LBM_LAUNCH_PER_LATTICE) return launch_step_batched(s);
+    if (cfg.mode != LBM_LAUNCH_PER_LATTICE) return s.ntiles ? launch_step_batched(s) : hipSuccess;
     for (auto& L : h->lats) {
         hipError_t e = launch_step_single(s, L.dev);
         if (e != hipSuccess) return e;
@@ -583,6 +600,10 @@ extern "C" lbm_status lbm_set_boundaries(lbm_handle* h, int32_t k, const uint8_t
     h->device_bytes -= (int64_t)L.N;
     if (e != hipSuccess) return fail(LBM_EDEVICE, "flag upload failed: %s", hipGetErrorString(e));
     drop_graph(h);
+    L.host_flags.assign(flags, flags + L.N);
+    h->tiles_block = 0;                  // the tile tables depend on the flags
+    st = rebuild_tiles(h);
+    if (st != LBM_OK) return st;
     st = run_init(h, L, nullptr, nullptr);
     if (st != LBM_OK) return st;
     h->step = 0;

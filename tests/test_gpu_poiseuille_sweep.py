@@ -1,0 +1,95 @@
+"""Poiseuille accuracy sweep over the channel radius at constant Reynolds
+number and centre velocity (Sec. 4.1 and its figure of E against R:
+Re = 2 R u_max / nu = 10, u_max = 0.1, D3Q19 SRT, Guo force, mid-grid
+bounce-back; here a periodic slab 4 cells long, run for 3 R^2 / nu steps to
+steady state).  E is the relative L2 error against the parabola.  The paper
+states, and the bars below check with margins:
+
+* at small radius (R = 8) the staircase wall dominates and every format has
+  the same error (within 5 % of FP64);
+* FP32/FP32 matches FP64/FP64 at every radius (within 1 %);
+* going to larger R the error grows first for FP16 and FP16S (above FP64 at
+  R = 32, while FP16C is not) and later for FP16C (R = 128: FP16S above FP16C
+  above 5x FP64);
+* the posits P16_0S and P16_1S hold up better than FP16C at large R;
+* without DDF shifting the 16-bit formats become unfeasible (R = 128: FP16S
+  does not flow, FP16C is 5x worse than shifted), while FP32 is unaffected."""
+import pytest
+
+import lbm_workloads as wl
+from lbm_testlib import say
+
+pytestmark = pytest.mark.gpu
+
+RE, UMAX, NX = 10.0, 0.1, 4
+FORMATS = ["fp64", "fp32", "fp16", "fp16s", "fp16c", "p16_0s", "p16_1s", "p16_2c"]
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_08926_amd as lbm
+    return lbm
+
+
+def _error(lbm, R, fmt, unshifted=False):
+    nu = 2 * R * UMAX / RE
+    tau = 3 * nu + 0.5
+    force = 4 * nu * UMAX / R ** 2                 # u_max = F R^2 / (4 nu)
+    ny = nz = 2 * (R + 1)
+    steps = int(3 * R * R / nu) // 100 * 100 + 100
+    flags = wl.poiseuille_flags(NX, ny, nz, R)
+    u_ref = wl.poiseuille_profile(NX, ny, nz, R, force, nu)
+    arith = "fp64" if fmt == "fp64" else "fp32"
+    p = lbm.make_params(NX, ny, nz, storage=fmt, arith=arith, tau=tau, force=(force, 0, 0), unshifted=unshifted)
+    with lbm.Lattices(p) as g:
+        g.set_boundaries(0, flags)
+        g.set_launch(mode=2, block=256, graph_steps=100)
+        g.step(steps)
+        e = g.diagnostics(0, u_ref)["l2_error"]
+    say(f"poiseuille R={R} {fmt}{' unshifted' if unshifted else ''}: E={e:.4e}")
+    return e
+
+
+@pytest.fixture(scope="module")
+def sweep(lbm):
+    out = {}
+    for R in (8, 32, 128):
+        for fmt in FORMATS:
+            out[(R, fmt, False)] = _error(lbm, R, fmt)
+    for fmt in ("fp32", "fp16s", "fp16c"):
+        out[(128, fmt, True)] = _error(lbm, 128, fmt, unshifted=True)
+    return out
+
+
+def test_small_radius_all_formats_alike(sweep):
+    e64 = sweep[(8, "fp64", False)]
+    for fmt in FORMATS:
+        assert abs(sweep[(8, fmt, False)] / e64 - 1) < 0.05, fmt
+
+
+@pytest.mark.parametrize("R", [8, 32, 128])
+def test_fp32_matches_fp64(sweep, R):
+    assert abs(sweep[(R, "fp32", False)] / sweep[(R, "fp64", False)] - 1) < 0.01
+
+
+def test_16bit_error_grows_with_radius_fp16s_first(sweep):
+    e64 = sweep[(32, "fp64", False)]
+    assert sweep[(32, "fp16", False)] > 1.3 * e64
+    assert sweep[(32, "fp16s", False)] > 1.3 * e64
+    assert sweep[(32, "fp16c", False)] < 1.1 * e64
+    e64 = sweep[(128, "fp64", False)]
+    assert sweep[(128, "fp16s", False)] > sweep[(128, "fp16c", False)] > 5 * e64
+
+
+def test_posits_hold_up_at_large_radius(sweep):
+    for fmt in ("p16_0s", "p16_1s"):
+        assert sweep[(128, fmt, False)] < sweep[(128, "fp16c", False)], fmt
+
+
+def test_without_shifting_16bit_unfeasible(sweep):
+    assert sweep[(128, "fp16s", True)] > 0.9
+    assert sweep[(128, "fp16c", True)] > 5 * sweep[(128, "fp16c", False)]
+    assert abs(sweep[(128, "fp32", True)] / sweep[(128, "fp64", False)] - 1) < 0.1
