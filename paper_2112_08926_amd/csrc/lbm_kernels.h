@@ -527,9 +527,12 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
 
     // The DDF loads go out together with the flag load (every address is in
     // the lattice whatever the flag), so a wavefront waits for memory once.
+    // Formats whose decoding dominates (the posits) do better loading after
+    // the flag, for fluid cells only (measured: 4-6 % on the 512^3 cavity).
     A f[Q], fo[Q];
-    pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
+    if (Codec<F>::kSpeculativeLoads || !special)
+        pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
     if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
     const bool any_eq = __any((fl & F_EQ) != 0);
     const size_t plane = L.plane;
