@@ -85,7 +85,7 @@ def measure_format(storage, n, steps, warmup):
     g, flags = cavity(n, storage)
     try:
         g.step(2)
-        cfg = g.autotune(3)                      # leaves the state unchanged
+        cfg = g.autotune(5)                      # leaves the state unchanged
         ms = time_steps(g, steps, warmup)
         d = g.diagnostics(0)
     finally:

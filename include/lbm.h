@@ -207,10 +207,12 @@ lbm_status lbm_diagnostics(lbm_handle* h, int32_t lattice, const double* u_ref, 
 lbm_status lbm_set_launch(lbm_handle* h, const lbm_launch* cfg);
 lbm_status lbm_get_launch(lbm_handle* h, lbm_launch* cfg);
 
-/* Time every launch configuration on the handle's own lattices (trial_steps
- * kernel launches each, reading the current state and writing the other
- * buffer, so the state is left unchanged), keep the fastest and return it.
- * The graph setting of the current configuration is kept. */
+/* Time every launch configuration on the handle's own lattices (one warm-up
+ * launch, then the better of two runs of trial_steps launches, each reading
+ * the current state and writing the other buffer, so the state is left
+ * unchanged), keep the fastest (ties within 0.5 % go to the candidate tried
+ * first, the smaller workgroup) and return it.  The graph setting of the
+ * current configuration is kept. */
 lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launch* best);
 
 lbm_status lbm_info_get(lbm_handle* h, lbm_info* out);

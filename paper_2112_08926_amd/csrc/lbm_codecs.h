@@ -45,16 +45,15 @@ template <int ES>
 __host__ __device__ __forceinline__ float posit_s_decode(uint32_t c) {
     const uint32_t mag = c & 0x7FFFu;
     const uint32_t t = mag << 17;
-    const uint32_t ones = t >> 31;                       // regime of ones (r >= 0)
-    const uint32_t u = ones ? ~t : t;                    // turn the run into zeros
-    const int k = __builtin_clz(u | 1u);                 // run length (mag != 0)
-    const int r = ones ? k - 1 : -k;
-    const uint32_t rest = (t << k) << 1;                 // bits after the terminator
+    const uint32_t s = (uint32_t)((int32_t)t >> 31);     // all ones for a regime of ones (r >= 0)
+    const int k = __builtin_clz((t ^ s) | 1u);           // run length (mag != 0)
+    const int r = (k - 1) ^ (int)~s;                     // k - 1 for ones, -k for zeros
+    const uint32_t sh = t << k;                          // the terminator at bit 31
     uint32_t bits;
     if (ES == 0)
-        bits = (uint32_t)((r + 120) << 23) + (rest >> 9);
+        bits = ((uint32_t)r << 23) + ((sh >> 8) & 0x7FFFFFu) + (120u << 23);
     else
-        bits = (uint32_t)((2 * r + 120) << 23) + (rest >> 8);   // exponent bit lands on bit 23
+        bits = ((uint32_t)r << 24) + ((sh >> 7) & 0xFFFFFFu) + (120u << 23);   // exponent bit on bit 23
     bits = mag ? bits : 0u;
     return u2f(bits | ((c & 0x8000u) << 16));
 }

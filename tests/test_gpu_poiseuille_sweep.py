@@ -13,7 +13,11 @@ states, and the bars below check with margins:
   above 5x FP64);
 * the posits P16_0S and P16_1S hold up better than FP16C at large R;
 * without DDF shifting the 16-bit formats become unfeasible (R = 128: FP16S
-  does not flow, FP16C is 5x worse than shifted), while FP32 is unaffected."""
+  does not flow, FP16C is 5x worse than shifted), while FP32 is unaffected;
+* radially (R = 63, the paper's radial error profile), FP64 and FP32 take
+  most of their error from the outer ring at the staircase wall, FP16S most
+  of its error from the inner ring around the axis."""
+import numpy as np
 import pytest
 
 import lbm_workloads as wl
@@ -34,7 +38,7 @@ def lbm():
     return lbm
 
 
-def _error(lbm, R, fmt, unshifted=False):
+def _run(lbm, R, fmt, unshifted=False, field=False):
     nu = 2 * R * UMAX / RE
     tau = 3 * nu + 0.5
     force = 4 * nu * UMAX / R ** 2                 # u_max = F R^2 / (4 nu)
@@ -49,8 +53,13 @@ def _error(lbm, R, fmt, unshifted=False):
         g.set_launch(mode=2, block=256, graph_steps=100)
         g.step(steps)
         e = g.diagnostics(0, u_ref)["l2_error"]
+        u = g.get_rho_u(0)[1] if field else None
     say(f"poiseuille R={R} {fmt}{' unshifted' if unshifted else ''}: E={e:.4e}")
-    return e
+    return (e, u, u_ref) if field else e
+
+
+def _error(lbm, R, fmt, unshifted=False):
+    return _run(lbm, R, fmt, unshifted)
 
 
 @pytest.fixture(scope="module")
@@ -93,3 +102,22 @@ def test_without_shifting_16bit_unfeasible(sweep):
     assert sweep[(128, "fp16s", True)] > 0.9
     assert sweep[(128, "fp16c", True)] > 5 * sweep[(128, "fp16c", False)]
     assert abs(sweep[(128, "fp32", True)] / sweep[(128, "fp64", False)] - 1) < 0.1
+
+
+@pytest.mark.parametrize("fmt,where", [("fp64", "wall"), ("fp32", "wall"), ("fp16s", "centre")])
+def test_radial_error_profile(lbm, fmt, where):
+    """Squared velocity error summed over two rings of equal area, the inner
+    r <= R/sqrt(2) and the outer: the outer ring, at the staircase wall,
+    carries most of it for FP64 and FP32, the inner one for FP16S
+    (floating-point errors accumulating ring by ring towards the centre)."""
+    R = 63
+    _, u, u_ref = _run(lbm, R, fmt, field=True)
+    ny = nz = 2 * (R + 1)
+    r = np.broadcast_to(wl.poiseuille_radius(ny, nz)[:, :, None], (nz, ny, NX)).reshape(-1)
+    inside = r <= R
+    err2 = ((u - u_ref) ** 2).sum(axis=0)
+    split = R / np.sqrt(2.0)
+    centre = err2[inside & (r <= split)].sum()
+    wall = err2[inside & (r > split)].sum()
+    say(f"radial {fmt}: centre half {centre:.3e}, wall half {wall:.3e}")
+    assert (centre > wall) if where == "centre" else (wall > centre)
