@@ -3,7 +3,8 @@
 //
 // Decoders are branch-free bit manipulation (one leading-zero count for the
 // posits).  FP16 and FP16S use the hardware f32<->f16 conversions (round to
-// nearest even).  FP16C and the posits encode through a 256-entry table
+// nearest even).  FP16C encodes arithmetically (fp16c_encode).  The posits
+// encode through a 256-entry table
 // indexed by the FP32 exponent field: inside one FP32 binade the codes of
 // these formats are either evenly spaced (code = first code + rounded
 // mantissa, the carry running into the next binade) or absent (one threshold
@@ -34,6 +35,27 @@ __host__ __device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit
 __host__ __device__ __forceinline__ float fp16c_decode(uint32_t c) {
     const uint32_t bits = ((c & 0x8000u) << 16) | ((c & 0x7FFFu) << 12);
     return u2f(bits) * 0x1p112f;
+}
+
+// Nearest FP16C code, ties away from zero, saturating at 0x7FFF (NaN too).
+// |x| >= 2^-14: the FP32 bits rebiased by 112 in the exponent, rounded at
+// the 12th bit (a carry moves to the next binade by itself).  Below: the
+// denormal codes are the multiples of 2^-25, so the code is |x| 2^25 rounded
+// half up (exact in float except just below 0.5, where y + 0.5 would round
+// to 1: those round to 0).  Checked against the exact table encoder on all
+// 2^32 floats.
+__host__ __device__ __forceinline__ uint16_t fp16c_encode(float x) {
+    const uint32_t b = f2u(x);
+    const uint32_t a = b & 0x7FFFFFFFu;
+    uint32_t code;
+    if (a >= (113u << 23)) {
+        code = (a - (112u << 23) + 0x800u) >> 12;
+        code = code < 0x7FFFu ? code : 0x7FFFu;
+    } else {
+        const float y = u2f(a) * 0x1p25f;
+        code = y < 0.5f ? 0u : (uint32_t)(y + 0.5f);
+    }
+    return (uint16_t)(((b >> 16) & 0x8000u) | code);
 }
 
 // ---------------------------------------------------------------- posits
@@ -164,10 +186,10 @@ template <> struct Codec<S_FP16S> {
 template <> struct Codec<S_FP16C> : RawCodec<S_FP16C> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
-    static constexpr bool kTable = true;
+    static constexpr bool kTable = false;            // arithmetic encoder
     static constexpr bool kSpeculativeLoads = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return fp16c_decode(v); }
-    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return fp16c_encode(v); }
 };
 template <> struct Codec<S_P16_0S> : RawCodec<S_P16_0S> {
     using T = uint16_t;

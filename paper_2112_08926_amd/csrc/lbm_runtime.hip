@@ -42,7 +42,8 @@ extern "C" const char* lbm_last_error(void) { return g_err.c_str(); }
 
 #include "lbm_enc_table.h"
 
-static bool uses_table(int storage) { return storage >= S_FP16C && storage <= S_P16_2C; }
+// FP16C encodes arithmetically; the posits through a table
+static bool uses_table(int storage) { return storage >= S_P16_0S && storage <= S_P16_2C; }
 
 static int ddf_bytes(int storage) { return storage == S_FP64 ? 8 : (storage == S_FP32 ? 4 : 2); }
 
@@ -155,6 +156,7 @@ __global__ void __launch_bounds__(256) k_encode(int storage, const float* __rest
         switch (storage) {
         case S_FP16: c = Codec<S_FP16>::store<float>(x, nullptr); break;
         case S_FP16S: c = Codec<S_FP16S>::store<float>(x, nullptr); break;
+        case S_FP16C: c = Codec<S_FP16C>::store<float>(x, nullptr); break;
         default: c = table_encode(x, s_tab); break;
         }
         out[i] = c;
