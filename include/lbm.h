@@ -192,9 +192,12 @@ lbm_status lbm_get_rho_u(lbm_handle* h, int32_t lattice, double* rho, double* u)
 
 /* Raw DDF codes of the current state: host buffer of q*N elements of the
  * storage type (double, float or uint16), direction-major [i*N + n].
- * set: copies in, to both DDF buffers so that cells the step never writes
- * (SOLID, EQ) hold the same codes in both (any values; used for checkpoints
- * and exact comparisons); get: copies out.  Both synchronise. */
+ * set: copies in, to both DDF buffers (used for checkpoints and exact
+ * comparisons); get: copies out.  Both synchronise.  Every step writes the
+ * code of +0 into SOLID cells and the stored equilibrium of eq_rho/eq_u
+ * into EQ cells (what lbm_set_rho_u puts there), so codes set into those
+ * cells other than these last until the next step: EQ codes are streamed
+ * to the neighbours once, SOLID codes are never read. */
 lbm_status lbm_set_ddf(lbm_handle* h, int32_t lattice, const void* host);
 lbm_status lbm_get_ddf(lbm_handle* h, int32_t lattice, void* host);
 

@@ -202,3 +202,19 @@ def random_noise(q, N, seed, amp=1e-3):
     """Non-equilibrium perturbation of the DDFs, uniform in +- amp."""
     rng = np.random.default_rng(seed + 7919)
     return amp * (2.0 * rng.random((q, N)) - 1.0)
+
+
+# --------------------------------------------------------------------------
+# Full-size synthetic states, drawn plane by plane
+# --------------------------------------------------------------------------
+def uniform_table(size, amp, seed):
+    """`size` values uniform in +- amp (sorted), the entries a full-size
+    state draws from."""
+    rng = np.random.default_rng(seed)
+    return np.sort(amp * (2.0 * rng.random(size) - 1.0))
+
+
+def table_indices(N, seed, plane, size):
+    """N seeded indices uniform in [0, size) for one direction plane of a
+    full-size state (numpy PCG64 seeded with (seed, plane))."""
+    return np.random.default_rng([seed, plane]).integers(0, size, N, dtype=np.uint16)

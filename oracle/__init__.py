@@ -72,6 +72,11 @@ class _Lattice(ctypes.Structure):
 
 
 def _ptr(a, ctype):
+    """Pointer to the data of an array laid out as the C side reads it:
+    C-contiguous, elements of the C type's size (an F-ordered view, which
+    numpy returns e.g. for a[:, index_array], would be read scrambled)."""
+    if not a.flags.c_contiguous or a.dtype.itemsize != ctypes.sizeof(ctype):
+        raise ValueError(f"array passed to the reference must be C-contiguous {ctype.__name__}")
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
@@ -190,6 +195,18 @@ class Lattice:
                       else np.ascontiguousarray(flags, dtype=np.uint8).reshape(self.N))
         self.f = np.zeros((self.q, self.N), dtype=np.float64)
         self.t = 0
+
+    @property
+    def f(self) -> np.ndarray:
+        """DDFs [q, N] in FP64; any array assigned is copied to C order."""
+        return self._f
+
+    @f.setter
+    def f(self, value):
+        v = np.ascontiguousarray(value, dtype=np.float64)
+        if v.shape != (self.q, self.N):
+            raise ValueError(f"DDF array of shape {v.shape}, expected {(self.q, self.N)}")
+        self._f = v
 
     def init(self, rho=None, u=None):
         """DDFs = stored equilibrium of rho[N] and u[3, N] (rest state if None)."""

@@ -7,10 +7,13 @@ same arguments in Python form; ``Lattices`` wraps a handle.
 from __future__ import annotations
 
 import ctypes
+import hashlib
 import os
 
 import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library shares with torch)
+
+from . import tuning
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblbm.so")
@@ -118,6 +121,21 @@ def library():
         fn.argtypes = args
     _lib = L
     return L
+
+
+_LIB_ID = None
+
+
+def library_id() -> str:
+    """SHA-256 of liblbm.so: names the build in the autotuning cache."""
+    global _LIB_ID
+    if _LIB_ID is None:
+        h = hashlib.sha256()
+        with open(_LIB_PATH, "rb") as fh:
+            for chunk in iter(lambda: fh.read(1 << 20), b""):
+                h.update(chunk)
+        _LIB_ID = h.hexdigest()
+    return _LIB_ID
 
 
 def lbm_last_error() -> str:
@@ -275,6 +293,7 @@ class Lattices:
         self.params = [params] if isinstance(params, LbmParams) else list(params)
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self._alloc = _TorchAllocator(self.stream) if torch_alloc else None
+        self.device = torch.cuda.current_device()
         self.h = lbm_create(self.params, self.stream, self._alloc)
         self.q = self.params[0].q
         self.storage = self.params[0].storage
@@ -321,8 +340,27 @@ class Lattices:
     def launch(self) -> dict:
         return lbm_get_launch(self.h).as_dict()
 
-    def autotune(self, trial_steps: int = 5) -> dict:
-        return lbm_autotune(self.h, trial_steps).as_dict()
+    def autotune(self, trial_steps: int = 5, cache: str | None = None) -> dict:
+        """Autotune the launch (lbm_autotune) and return it.  With `cache` (a
+        JSON file path), a configuration cached for this ensemble, device and
+        library build is applied instead of timing, and a new result is
+        added to the file.  A cached entry the library rejects is tuned
+        again and replaced."""
+        if cache is None:
+            return lbm_autotune(self.h, trial_steps).as_dict()
+        props = torch.cuda.get_device_properties(self.device)
+        key = tuning.ensemble_key(self.params, f"{props.name}|{props.gcnArchName}", library_id())
+        hit = tuning.load(cache, key)
+        if hit is not None:
+            try:
+                self.set_launch(**hit)
+                return self.launch()
+            except LbmError:
+                pass
+        best = lbm_autotune(self.h, trial_steps).as_dict()
+        p = self.params[0]
+        tuning.store(cache, key, best, note=f"q={p.q} storage={p.storage} lattices={len(self.params)}")
+        return best
 
     def info(self) -> dict:
         i = lbm_info_get(self.h)

@@ -49,7 +49,7 @@ def ref_codes(orc, storage: str, f: np.ndarray) -> np.ndarray:
 
 def decode_codes(orc, storage: str, codes: np.ndarray) -> np.ndarray:
     if storage in ("fp64", "fp32"):
-        return codes.astype(np.float64)
+        return np.ascontiguousarray(codes, dtype=np.float64)
     return orc.decode(storage, codes)
 
 
@@ -99,3 +99,82 @@ def one_step_inputs(nx, ny, nz, q, seed, solid_frac=0.05, with_eq=True, with_mov
         f3[:, 0, :] = np.where(f3[:, 0, :] & wl.SOLID, f3[:, 0, :], wl.EQ)
     rho, u = wl.random_fields(N, seed)
     return flags, rho, u
+
+
+# ------------------------------------------------------------ sampled parity at full size
+AMP, TABLE = 0.05, 4096
+
+
+def synthetic_codes(orc, storage, q, N, seed, indices=None):
+    """Stored codes [q, N]: direction i draws from the codes of w_i * a over
+    a seeded table of a values (uniform in +-AMP), plane by plane."""
+    _, w, _ = orc.velset(q)
+    a = wl.uniform_table(TABLE, AMP, seed)
+    table = ref_codes(orc, storage, w[:, None] * a[None, :])
+    out = np.empty((q, N), dtype=table.dtype)
+    for i in range(q):
+        idx = indices[i] if indices is not None else wl.table_indices(N, seed, i, TABLE)
+        np.take(table[i], idx, out=out[i])
+    return out
+
+
+def sample_points(dims, rng, n_random=1200, extra=None):
+    """Distinct (x, y, z): the product of special coordinates per axis (both
+    ends, their neighbours, the ends of 256-cell segments), random cells and
+    `extra`."""
+    axes = []
+    for n in dims:
+        s = {0, 1, 2, n - 3, n - 2, n - 1, n // 2}
+        s |= {v for v in (255, 256, 257, 511, 512) if v < n}
+        axes.append(sorted(v for v in s if 0 <= v < n))
+    g = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    r = np.stack([rng.integers(0, n, n_random) for n in dims], axis=1)
+    parts = [g, r] + ([np.asarray(extra).reshape(-1, 3)] if extra is not None else [])
+    pts = np.concatenate(parts).astype(np.int64)
+    nx, ny = dims[0], dims[1]
+    _, keep = np.unique(pts[:, 0] + nx * (pts[:, 1] + ny * pts[:, 2]), return_index=True)
+    return pts[np.sort(keep)]
+
+
+def check_samples(orc, storage, q, collision, tau, dims, flags, codes_in, codes_out, pts, label,
+                  force=(0.0, 0.0, 0.0), wall_u=(0.0, 0.0, 0.0)):
+    """Reference step of each sampled cell from its 3x3x3 neighbourhood;
+    returns the fraction of identical codes and the number of compared
+    non-wall cells.  Wall cells must keep their codes exactly; EQ cells are
+    compared like fluid cells (the reference keeps the input's equilibrium
+    codes, the device writes its own, which may round differently)."""
+    nx, ny, nz = dims
+    S = len(pts)
+    off = np.arange(3) - 1
+    X = (pts[:, 0][:, None] + off) % nx                   # [S, 3]: x - 1, x, x + 1
+    Y = (pts[:, 1][:, None] + off) % ny
+    Z = (pts[:, 2][:, None] + off) % nz
+    # small lattice (3S, 3, 3): cell a + 3k + 3S (b + 3c) holds (X[k,a], Y[k,b], Z[k,c])
+    big = (X[None, None, :, :] + nx * (Y.T[None, :, :, None] + ny * Z.T[:, None, :, None])).reshape(-1)
+    centre_big = pts[:, 0] + nx * (pts[:, 1] + ny * pts[:, 2])
+    centre_small = 3 * np.arange(S) + 1 + 12 * S
+    fl3 = flags[big]
+    ref = orc.Lattice(3 * S, 3, 3, q=q, tau=tau, collision=collision, storage=storage, force=force,
+                      wall_u=wall_u, flags=fl3)
+    ref.f = decode_codes(orc, storage, codes_in[:, big])
+    ref.step(1)
+    exp = ref.f[:, centre_small]
+    got = codes_out[:, centre_big]
+    solid = (flags[centre_big] & wl.SOLID) != 0
+    assert np.array_equal(got[:, solid], codes_in[:, centre_big][:, solid]), label
+    same = assert_step_parity(orc, storage, got[:, ~solid], exp[:, ~solid], label)
+    return same, int((~solid).sum())
+
+
+def model_walls(orc, storage, q, codes, flags, eq_rho=1.0, eq_u=(0.0, 0.0, 0.0)):
+    """Put into SOLID cells the code of 0 and into EQ cells the stored
+    equilibrium of (eq_rho, eq_u): what the model holds there (and what a
+    step writes there), in place."""
+    zero = ref_codes(orc, storage, np.zeros(q))
+    eq = ref_codes(orc, storage, orc.equilibrium(q, eq_rho, np.asarray(eq_u, dtype=np.float64)))
+    solid = np.flatnonzero(flags & wl.SOLID)
+    eqm = np.flatnonzero((flags & (wl.EQ | wl.SOLID)) == wl.EQ)
+    for i in range(q):
+        codes[i][solid] = zero[i]
+        codes[i][eqm] = eq[i]
+    return codes

@@ -1,5 +1,6 @@
 """GPU parity: the HIP path through the C interface against the FP64 CPU
 reference on the same seeded inputs."""
+import json
 import math
 
 import numpy as np
@@ -281,6 +282,44 @@ def test_autotune_keeps_state(lbm):
             g.step(2)
             res.append(g.get_ddf(0))
     assert np.array_equal(res[0], res[1])
+
+
+def test_autotune_json_cache(lbm, tmp_path, monkeypatch):
+    """The first tuning of an ensemble is written to the JSON cache; a second
+    handle of the same ensemble applies the cached launch without timing (the
+    tuner is replaced by one that fails), keeps its own graph setting, and
+    steps bit-identically; an entry the library rejects is tuned again."""
+    import paper_2112_08926_amd._lib as lib_mod
+    cache = str(tmp_path / "tune.json")
+    n = 48
+    flags = wl.cavity_flags(n, n, n)
+    p = lbm.make_params(n, n, n, collision="trt", storage="fp16s", tau=0.6, wall_u=(0, 0.1, 0))
+    with lbm.Lattices(p) as g:
+        g.set_boundaries(0, flags)
+        best = g.autotune(2, cache=cache)
+        g.step(4)
+        ref = g.get_ddf(0)
+    real = lib_mod.lbm_autotune
+
+    def refuse(h, steps):
+        raise AssertionError("tuned although cached")
+    monkeypatch.setattr(lib_mod, "lbm_autotune", refuse)
+    with lbm.Lattices(p) as g:
+        g.set_boundaries(0, flags)
+        g.set_launch(graph_steps=2)
+        hit = g.autotune(2, cache=cache)
+        say("cached launch", hit)
+        assert {k: hit[k] for k in lbm.tuning.LAUNCH_FIELDS} == {k: best[k] for k in lbm.tuning.LAUNCH_FIELDS}
+        assert hit["graph_steps"] == 2
+        g.step(4)
+        assert np.array_equal(g.get_ddf(0), ref)
+    key = next(iter(json.load(open(cache))))
+    lbm.tuning.store(cache, key, dict(best, block=7))          # not a valid workgroup size
+    monkeypatch.setattr(lib_mod, "lbm_autotune", real)
+    with lbm.Lattices(p) as g:
+        g.set_boundaries(0, flags)
+        again = g.autotune(2, cache=cache)
+        assert again["block"] != 7 and lbm.tuning.load(cache, key)["block"] == again["block"]
 
 
 def test_staged_batched_ensemble_bit_identical(lbm):
