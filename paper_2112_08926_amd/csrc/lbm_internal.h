@@ -20,6 +20,7 @@ struct LatDev {
     void* f[2];              // DDF buffers: q planes of `plane` elements each
     const uint8_t* flags;    // one byte per cell
     const uint32_t* wall_mask; // per cell: bit i = source x - c_i is a wall, bit 31 = one of them moves
+    const uint32_t* near_bits; // bit g: one of the cells 64g .. 64g+63 has a wall source (F_NEAR)
     uint32_t nx, ny, nz;
     uint32_t plane;          // elements between consecutive direction planes
     double omega;            // 1/tau (TRT: symmetric rate)

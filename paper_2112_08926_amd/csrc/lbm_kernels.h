@@ -175,40 +175,78 @@ __device__ __forceinline__ A load_ddf(typename Codec<F>::T v) {
 template <int F, bool RAW>
 constexpr double raw_scale() { return RAW ? (double)(1u << Codec<F>::kRawExp) : 1.0; }
 
+// Whether a wavefront whose cells lie in n_first .. n_first + 63 holds a cell
+// with a wall source: bits g and g + 1 (g = n_first / 64) of the lattice's
+// group bitmap, read with one scalar load before any DDF load is issued.
+// A lattice without walls has no bitmap (null) and skips the read.
+__device__ __forceinline__ bool wave_has_walls(const LatDev& L, uint32_t n_first) {
+    if (L.near_bits == nullptr) return false;
+    typedef const __attribute__((address_space(4))) uint32_t* ConstPtr;
+    const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)(n_first >> 6));
+    const ConstPtr b = (ConstPtr)(const void*)L.near_bits + (g >> 5);
+    const uint64_t v = (uint64_t)b[0] | ((uint64_t)b[1] << 32);
+    return ((v >> (g & 31)) & 3u) != 0;
+}
+
 // LANE_ROWS: the row bases differ between lanes (cell-contiguous tiles), so
 // the whole in-plane index is the per-lane offset; otherwise the row base
 // is wavefront-uniform and folded into the scalar base address.
+// walls (wavefront-uniform): some cell of the wavefront may have a wall
+// source.  A wall source hands back what this cell sent towards it last
+// step, its own opposite DDF: such a direction takes that address in the
+// same load instruction (chosen per lane from the cell's wall mask), so a
+// wavefront next to a wall issues one extra load (the mask), not one per
+// bounced direction.
 template <int Q, int F, class A, bool RAW, bool LANE_ROWS = false>
 __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
                                      const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp,
-                                     uint32_t n, bool near, A (&f)[Q]) {
+                                     uint32_t n, bool walls, A (&f)[Q]) {
     using T = typename Codec<F>::T;
     const size_t plane = L.plane;
+    if (!walls) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            if constexpr (LANE_ROWS) {
+                f[i] = load_ddf<Q, F, A, RAW>(ld_off(src + (size_t)i * plane, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)));
+            } else {
+                const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
+                f[i] = load_ddf<Q, F, A, RAW>(ld_off(p, src_x<Q>(i, x, xm, xp)));
+            }
+        }
+        return;
+    }
+    const uint32_t m = ld_off(L.wall_mask, n);
+    // All Q loads first, addresses chosen by selects (no branch between the
+    // loads, so they are all in flight at once) ...
 #pragma unroll
     for (int i = 0; i < Q; i++) {
+        const T* p;
+        uint32_t idx;
         if constexpr (LANE_ROWS) {
-            f[i] = load_ddf<Q, F, A, RAW>(ld_off(src + (size_t)i * plane, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)));
+            p = src + (size_t)i * plane;
+            idx = src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp);
         } else {
-            const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
-            f[i] = load_ddf<Q, F, A, RAW>(ld_off(p, src_x<Q>(i, x, xm, xp)));
+            p = src + ((size_t)i * plane + src_row<Q>(rc, i));
+            idx = src_x<Q>(i, x, xm, xp);
         }
+        if (i > 0) {
+            const bool wall = (m >> i) & 1u;
+            p = wall ? src + (size_t)opp(i) * plane : p;
+            idx = wall ? n : idx;
+        }
+        f[i] = load_ddf<Q, F, A, RAW>(ld_off(p, idx));
     }
-    if (__any(near)) {
-        // A wall source hands back what this cell sent towards it last step.
-        const uint32_t m = near ? ld_off(L.wall_mask, n) : 0u;
+    // ... then the moving walls' momentum, only in wavefronts next to one.
+    if (__any((m & 0x80000000u) != 0)) {
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            if (m & (1u << i)) {
-                A v = load_ddf<Q, F, A, RAW>(ld_off(src + (size_t)opp(i) * plane, n));
-                if (m & 0x80000000u) {
-                    const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
-                    if (fs & F_MOVING) {
-                        const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
-                                         VelSet<Q>::c[i][2] * L.wall_u[2]);
-                        v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, RAW>()) * cu;
-                    }
+            if (((m >> i) & 1u) && (m & 0x80000000u)) {
+                const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
+                if (fs & F_MOVING) {
+                    const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                     VelSet<Q>::c[i][2] * L.wall_u[2]);
+                    f[i] += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, RAW>()) * cu;
                 }
-                f[i] = v;
             }
         }
     }
@@ -531,8 +569,9 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     // the flag, for fluid cells only (measured: 4-6 % on the 512^3 cavity).
     A f[Q], fo[Q];
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
+    const bool walls = wave_has_walls(L, n);
     if (Codec<F>::kSpeculativeLoads || !special)
-        pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+        pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, walls, f);
     if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
     const bool any_eq = __any((fl & F_EQ) != 0);
     const size_t plane = L.plane;
@@ -580,7 +619,7 @@ __device__ __forceinline__ void step_tile_dense(const LatDev& L, uint32_t x0, ui
     T* __restrict__ dst = (T*)L.f[parity ^ 1];
 
     A f[Q], fo[Q];
-    pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);   // loads with the flag's
+    pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);   // loads with the flag's
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
     if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
     const bool any_eq = __any((fl & F_EQ) != 0);
@@ -1133,7 +1172,7 @@ __device__ __forceinline__ void cell_moments(const LatDev& L, int parity, uint32
         make_rows(L, y, z, rc);
         const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
         const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
-        pull<Q, F, A, false>(L, src, rc, x, xm, xp, n, (fl & F_NEAR) != 0, f);
+        pull<Q, F, A, false>(L, src, rc, x, xm, xp, n, __any((fl & F_NEAR) != 0), f);
         fields<Q, A>(f, (A)L.shift, rho, j);
         if (L.forced) {
             for (int a = 0; a < 3; a++) j[a] += (A)0.5 * (A)L.force[a];

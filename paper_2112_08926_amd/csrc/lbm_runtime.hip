@@ -199,6 +199,40 @@ __global__ void __launch_bounds__(256) k_mark_near(const uint8_t* __restrict__ r
     mask[n] = m;
 }
 
+// Bit g (bit g % 32 of word g / 32) of `bits`: one of the cells 64g ..
+// 64g+63 (below N) has a wall source (F_NEAR).  One lane per group of 64
+// cells; each wavefront's 64 bits are two whole words, written by its first
+// lane.  `waves` wavefronts cover every group plus one pair of zero words,
+// which the step's two-word read at the last group reaches.
+__global__ void __launch_bounds__(256) k_near_groups(const uint8_t* __restrict__ flags, uint32_t* __restrict__ bits,
+                                                     size_t N, size_t waves) {
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t wave = g >> 6;
+    if (wave >= waves) return;                       // whole wavefronts
+    bool near = false;
+    const size_t n0 = g * 64;
+    if (n0 + 64 <= N) {
+        const uint4* p = (const uint4*)(flags + n0);  // 16-byte aligned: n0 is a multiple of 64
+        for (int k = 0; k < 4; k++) {
+            const uint4 v = p[k];
+            near |= ((v.x | v.y | v.z | v.w) & 0x08080808u) != 0;   // F_NEAR in any byte
+        }
+    } else {
+        for (size_t n = n0; n < N; n++) near |= (flags[n] & F_NEAR) != 0;
+    }
+    const uint64_t b = __ballot(near);
+    if ((threadIdx.x & 63) == 0) {
+        bits[2 * wave] = (uint32_t)b;
+        bits[2 * wave + 1] = (uint32_t)(b >> 32);
+    }
+}
+
+// Words of the group bitmap of a lattice of N cells (see k_near_groups).
+static size_t near_words(size_t N) {
+    const size_t groups = (N + 63) / 64;
+    return 2 * ((groups + 63) / 64 + 1);
+}
+
 // One 16-byte element per lane, streamed with nontemporal loads and stores
 // (the fastest plain copy form measured on gfx950); grid-stride only beyond
 // 2^31 workgroups.
@@ -216,6 +250,8 @@ struct Lattice {
     void* f[2] = {nullptr, nullptr};
     uint8_t* flags = nullptr;
     uint32_t* wall_mask = nullptr;
+    uint32_t* near_bits = nullptr;   // one bit per 64 cells: some cell has a wall source
+    size_t near_words = 0;
     void* eq_codes = nullptr;   // q codes of the EQ state
     LatDev dev{};
     // host copy of the caller's flags (empty: no walls), for the tile tables:
@@ -287,6 +323,7 @@ static void fill_dev(Lattice& L, int arith) {
     d.f[1] = L.f[1];
     d.flags = L.flags;
     d.wall_mask = L.wall_mask;
+    d.near_bits = nullptr;           // no walls until lbm_set_boundaries says otherwise
     d.eq_codes = L.eq_codes;
     d.nx = (uint32_t)L.p.nx;
     d.ny = (uint32_t)L.p.ny;
@@ -399,13 +436,16 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
         L.f[1] = dev_alloc(h, bytes);
         L.flags = (uint8_t*)dev_alloc(h, L.N);
         L.wall_mask = (uint32_t*)dev_alloc(h, L.N * 4);
+        L.near_words = near_words(L.N);
+        L.near_bits = (uint32_t*)dev_alloc(h, L.near_words * 4);
         L.eq_codes = dev_alloc(h, 27 * 8);
-        if (!L.f[0] || !L.f[1] || !L.flags || !L.wall_mask || !L.eq_codes) {
+        if (!L.f[0] || !L.f[1] || !L.flags || !L.wall_mask || !L.near_bits || !L.eq_codes) {
             lbm_destroy(h);
             return fail(LBM_ENOMEM, "device allocation of lattice %d (%zu bytes per buffer) failed", k, bytes);
         }
         if (hipMemsetAsync(L.flags, 0, L.N, h->stream) != hipSuccess ||
             hipMemsetAsync(L.wall_mask, 0, L.N * 4, h->stream) != hipSuccess ||
+            hipMemsetAsync(L.near_bits, 0, L.near_words * 4, h->stream) != hipSuccess ||
             hipMemsetAsync(L.f[0], 0, bytes, h->stream) != hipSuccess ||
             hipMemsetAsync(L.f[1], 0, bytes, h->stream) != hipSuccess) {
             lbm_destroy(h);
@@ -449,6 +489,7 @@ extern "C" void lbm_destroy(lbm_handle* h) {
         dev_free(h, L.f[1]);
         dev_free(h, L.flags);
         dev_free(h, L.wall_mask);
+        dev_free(h, L.near_bits);
         dev_free(h, L.eq_codes);
     }
     dev_free(h, h->d_partials);
@@ -612,12 +653,26 @@ extern "C" lbm_status lbm_set_boundaries(lbm_handle* h, int32_t k, const uint8_t
         }
         e = hipGetLastError();
     }
+    if (e == hipSuccess) {
+        const size_t waves = L.near_words / 2;
+        hipLaunchKernelGGL(k_near_groups, dim3((unsigned)((waves * 64 + 255) / 256)), dim3(256), 0, h->stream,
+                           L.flags, L.near_bits, L.N, waves);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // fl is a local buffer
     dev_free(h, d_raw);
     h->device_bytes -= (int64_t)L.N;
     if (e != hipSuccess) return fail(LBM_EDEVICE, "flag upload failed: %s", hipGetErrorString(e));
     drop_graph(h);
     L.host_flags.assign(flags, flags + L.N);
+    // Lattices without walls skip the group bitmap in the step (its read is
+    // the one thing a wavefront waits for before its first DDF load).
+    bool any_solid = false;
+    for (size_t n = 0; n < L.N && !any_solid; n++) any_solid = (flags[n] & LBM_FLAG_SOLID) != 0;
+    L.dev.near_bits = any_solid ? L.near_bits : nullptr;
+    if (hipMemcpyAsync(h->d_lats + k, &L.dev, sizeof(LatDev), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return fail(LBM_EDEVICE, "descriptor upload failed");
     h->tiles_block = 0;                  // the tile tables depend on the flags
     st = rebuild_tiles(h);
     if (st != LBM_OK) return st;
