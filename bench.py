@@ -195,6 +195,48 @@ def ensemble(storage="fp16s", count=256, steps=50, warmup=10):
         g.close()
 
 
+def karman(storages=("fp16s", "fp16c", "fp32"), steps=50, warmup=10):
+    """The Karman channel at full size: 1024 x 256 x 64, D3Q27 TRT (magic
+    1/4), cylinder of radius 16 along z at (256, 128), equilibrium inflow and
+    outflow cells with u = 0.05 on the x and y faces, tau 0.532 (Re = 150 on
+    the diameter), FP32 arithmetic.  Per storage: MLUPs/s of the autotuned
+    step from the asymmetric start, and the FP64 momentum-exchange force on
+    the cylinder after the timed steps."""
+    import paper_2112_08926_amd as lbm
+    import lbm_workloads as wl
+    nx, ny, nz, R, u0, tau = 1024, 256, 64, 16.0, 0.05, 0.532
+    flags = wl.karman_flags(nx, ny, nz, R, nx / 4, ny / 2)
+    rho, u = wl.karman_fields(nx, ny, nz, u0)
+    N = nx * ny * nz
+    n_fluid = int(np.count_nonzero(flags == 0))
+    rows = []
+    for storage in storages:
+        p = lbm.make_params(nx, ny, nz, q=27, collision="trt", storage=storage, tau=tau,
+                            eq_rho=1.0, eq_u=(u0, 0.0, 0.0))
+        g = lbm.Lattices(p)
+        try:
+            g.set_boundaries(0, flags)
+            g.set_rho_u(0, rho, u)
+            g.step(2)
+            cfg = g.autotune(5)
+            ms = time_steps(g, steps, warmup)
+            d = g.diagnostics(0)
+        finally:
+            g.close()
+        alg = n_fluid * (2 * 27 * ddf_bytes(storage) + 1) + (N - n_fluid)
+        gbs = alg / (ms * 1e-3) / 1e9
+        rows.append({"storage": storage, "cells": N, "ms_per_step": round(ms, 4),
+                     "mlups": round(N / (ms * 1e-3) / 1e6, 1), "achieved_GBps": round(gbs, 1),
+                     "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
+                     "force_on_cylinder": [float(v) for v in d["force_on_solid"]],
+                     "nonfinite": d["nonfinite_cells"],
+                     "launch": {k: cfg[k] for k in ("block", "cells_per_lane", "staged")}})
+        print(f"[bench] karman D3Q27 {storage}: {rows[-1]['mlups']:.0f} MLUPs/s, {gbs:.0f} GB/s",
+              file=sys.stderr, flush=True)
+    return {"workload": "Karman channel 1024x256x64, D3Q27 TRT, cylinder R 16, EQ inflow/outflow u 0.05, "
+                        "tau 0.532 (Re 150)", "steps_from_start": steps + warmup + 2, "rows": rows}
+
+
 def copy_bandwidth(nbytes=4 << 30, reps=10):
     """Achievable HBM bandwidth of a plain device copy (the library's copy
     probe), counted as bytes read + bytes written."""
@@ -280,6 +322,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-lattice ensemble")
+    ap.add_argument("--no-karman", action="store_true", help="skip the full-size Karman channel (D3Q27)")
     ap.add_argument("--no-periodic", action="store_true",
                     help="skip the periodic-box runs (the paper's performance workload, other velocity sets)")
     args = ap.parse_args()
@@ -314,6 +357,10 @@ def main():
     if not args.no_ensemble:
         print("[bench] ensemble of 256 lattices", file=sys.stderr, flush=True)
         ens = ensemble()
+    kar = None
+    if not args.no_karman:
+        print("[bench] Karman channel 1024x256x64", file=sys.stderr, flush=True)
+        kar = karman()
     per = None
     if not args.no_periodic:
         print("[bench] periodic boxes", file=sys.stderr, flush=True)
@@ -350,6 +397,7 @@ def main():
                                   if "fp32" in results else None),
         "l2_vs_fp64": acc,
         "ensemble": ens,
+        "karman": kar,
         "periodic_box": per,
         "kernel_source_hash": kernel_source_hash(),
     }
