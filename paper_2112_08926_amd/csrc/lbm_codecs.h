@@ -126,8 +126,6 @@ __host__ __device__ __forceinline__ float decode16(int fmt, uint32_t c) {
 // ---------------------------------------------------------------- storage traits
 // Codec<F>::T is the stored type; load() returns the arithmetic value, store()
 // takes it.  `tab` is the encoder table in LDS (used by FP16C and posits).
-// kSpeculativeLoads: the step issues a cell's DDF loads before its flag has
-// arrived (see step_tile).
 // load_raw()/store_raw() work in units of 2^-kRawExp: the step kernel does
 // its arithmetic in those units (every constant scaled by 2^kRawExp; scaling
 // by a power of two is exact, so the result is the same), which removes the
@@ -148,7 +146,6 @@ template <> struct Codec<S_FP64> : RawCodec<S_FP64> {
     using T = double;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = false;
-    static constexpr bool kSpeculativeLoads = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return (A)v; }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return (T)v; }
 };
@@ -156,7 +153,6 @@ template <> struct Codec<S_FP32> : RawCodec<S_FP32> {
     using T = float;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = false;
-    static constexpr bool kSpeculativeLoads = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return (A)v; }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return (T)v; }
 };
@@ -164,7 +160,6 @@ template <> struct Codec<S_FP16> : RawCodec<S_FP16> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = false;
-    static constexpr bool kSpeculativeLoads = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return half_decode(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return half_encode(v); }
 };
@@ -172,7 +167,6 @@ template <> struct Codec<S_FP16S> {
     using T = uint16_t;
     static constexpr int kRawExp = 15;          // the stored FP16 value is x * 2^15
     static constexpr bool kTable = false;
-    static constexpr bool kSpeculativeLoads = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return half_decode(v) * 0x1p-15f; }
     // The 2^15 scale is an exponent add (ldexp: exact, keeps -0); a plain
     // multiply gets fused with the conversion into a multiply-add with a +0
@@ -187,7 +181,6 @@ template <> struct Codec<S_FP16C> : RawCodec<S_FP16C> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = false;            // arithmetic encoder
-    static constexpr bool kSpeculativeLoads = true;
     template <class A> __device__ __forceinline__ static A load(T v) { return fp16c_decode(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return fp16c_encode(v); }
 };
@@ -195,7 +188,6 @@ template <> struct Codec<S_P16_0S> : RawCodec<S_P16_0S> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
-    static constexpr bool kSpeculativeLoads = false;   // decoding-bound
     template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode<0>(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
 };
@@ -203,7 +195,6 @@ template <> struct Codec<S_P16_1S> : RawCodec<S_P16_1S> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
-    static constexpr bool kSpeculativeLoads = false;   // decoding-bound
     template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode<1>(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
 };
@@ -211,7 +202,6 @@ template <> struct Codec<S_P16_2C> : RawCodec<S_P16_2C> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
-    static constexpr bool kSpeculativeLoads = false;   // decoding-bound
     template <class A> __device__ __forceinline__ static A load(T v) { return p162c_decode(v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
 };

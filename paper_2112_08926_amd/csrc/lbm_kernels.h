@@ -20,8 +20,10 @@
 // per-lane x offset from {x-1, x, x+1}: no integer division per cell, and
 // each direction is one contiguous, coalesced segment of a source row.  A
 // row's x-shifted loads stay inside that row (periodic wrap), so a row's
-// cache lines are fetched by one workgroup only.  Neighbour flags are read
-// only by wavefronts that contain a cell next to a wall (F_NEAR).
+// cache lines are fetched by one workgroup only.  No neighbour flag is read
+// per direction: a per-cell mask of wall sources, precomputed with the
+// flags, is read only by wavefronts that a bitmap of 64-cell groups marks as
+// holding a cell next to a wall (F_NEAR).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -564,14 +566,11 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     T* __restrict__ dst = (T*)L.f[parity ^ 1];
 
     // The DDF loads go out together with the flag load (every address is in
-    // the lattice whatever the flag), so a wavefront waits for memory once.
-    // Formats whose decoding dominates (the posits) do better loading after
-    // the flag, for fluid cells only (measured: 4-6 % on the 512^3 cavity).
+    // the lattice whatever the flag), so a wavefront waits for memory once;
+    // wall and EQ cells load and decode too and then store what they keep.
     A f[Q], fo[Q];
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
-    const bool walls = wave_has_walls(L, n);
-    if (Codec<F>::kSpeculativeLoads || !special)
-        pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, walls, f);
+    pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
     if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
     const bool any_eq = __any((fl & F_EQ) != 0);
     const size_t plane = L.plane;
