@@ -11,9 +11,9 @@
  *     order, density summed with the 1 added last, velocity summed with
  *     alternating signs), the velocity clamp and mid-grid bounce-back of the
  *     paper's D3Q19 SRT kernel listing;
- *   - velocity sets D3Q19 and D3Q27, collision SRT (BGK) or TRT, Guo body
- *     force, stationary and moving bounce-back walls, cells held at a fixed
- *     equilibrium;
+ *   - velocity sets D2Q9, D3Q15, D3Q19 and D3Q27 (Table 1), collision SRT
+ *     (BGK), TRT or, for D3Q19, MRT; Guo body force, stationary and moving
+ *     bounce-back walls, cells held at a fixed equilibrium;
  *   - FP32 arithmetic with DDFs stored as FP32, IEEE FP16, FP16S, FP16C,
  *     P16_0S, P16_1S or P16_2C (Sec. 3, Table 2), and an FP64 arithmetic path
  *     with FP64 or FP32 storage;
