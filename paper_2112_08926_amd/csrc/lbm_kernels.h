@@ -529,23 +529,40 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
 // writes whole rows: a store that leaves holes in a cache line makes the
 // memory side read the line to merge it, which at a wall in every row cost
 // ~15 % of the 512^3 cavity's step.
-template <int Q, int F>
-__device__ __forceinline__ typename Codec<F>::T special_code(const LatDev& L, uint32_t fl, int i) {
+// The lattice's stored equilibrium code of direction i, the same for every
+// lane: read with scalar loads (16-bit codes two to a word), so that a
+// wavefront's Q codes arrive together instead of as Q dependent vector loads.
+template <int F>
+__device__ __forceinline__ typename Codec<F>::T eq_code(const LatDev& L, int i) {
     using T = typename Codec<F>::T;
-    return (fl & F_EQ) ? ld_off((const T*)L.eq_codes, (uint32_t)i) : (T)0;
+    if constexpr (sizeof(T) == 2) {
+        typedef const __attribute__((address_space(4))) uint32_t* ConstWords;
+        const uint32_t w = ((ConstWords)(const void*)L.eq_codes)[i >> 1];
+        return (T)((i & 1) ? (w >> 16) : (w & 0xFFFFu));
+    } else {
+        typedef const __attribute__((address_space(4))) T* ConstCodes;
+        return ((ConstCodes)(const void*)L.eq_codes)[i];
+    }
 }
-// The code cell (flags fl) stores for direction i: the collision's, or what
-// a wall or EQ cell keeps.  The EQ table is read only by wavefronts that
-// hold an EQ cell (any_eq), so other wavefronts issue no extra loads.
+// The Q equilibrium codes, read only if the wavefront holds an EQ cell
+// (any_eq, wavefront-uniform); zero otherwise.
 template <int Q, int F>
-__device__ __forceinline__ typename Codec<F>::T out_code(const LatDev& L, uint32_t fl, bool any_eq, int i,
+__device__ __forceinline__ void eq_codes_if(const LatDev& L, bool any_eq, typename Codec<F>::T (&e)[Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; i++) e[i] = 0;
+    if (any_eq) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) e[i] = eq_code<F>(L, i);
+    }
+}
+// The code a cell (flags fl) stores: the collision's, or what a wall (zero)
+// or EQ cell (its equilibrium code eq) keeps.
+template <int F>
+__device__ __forceinline__ typename Codec<F>::T out_code(uint32_t fl, typename Codec<F>::T eq,
                                                          typename Codec<F>::T code) {
     using T = typename Codec<F>::T;
     if (fl & F_SOLID) code = (T)0;
-    if (any_eq) {
-        const T e = ld_off((const T*)L.eq_codes, (uint32_t)i);
-        if (fl & F_EQ) code = e;
-    }
+    if (fl & F_EQ) code = eq;
     return code;
 }
 
@@ -572,12 +589,13 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
     pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
     if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
-    const bool any_eq = __any((fl & F_EQ) != 0);
+    T eq[Q];
+    eq_codes_if<Q, F>(L, __any((fl & F_EQ) != 0), eq);
     const size_t plane = L.plane;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         T* p = dst + ((size_t)i * plane + rc.rows[4]);
-        st_off(p, x, out_code<Q, F>(L, fl, any_eq, i, Codec<F>::template store_raw<A>(fo[i], tab)));
+        st_off(p, x, out_code<F>(fl, eq[i], Codec<F>::template store_raw<A>(fo[i], tab)));
     }
 }
 
@@ -621,11 +639,12 @@ __device__ __forceinline__ void step_tile_dense(const LatDev& L, uint32_t x0, ui
     pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);   // loads with the flag's
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
     if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
-    const bool any_eq = __any((fl & F_EQ) != 0);
+    T eq[Q];
+    eq_codes_if<Q, F>(L, __any((fl & F_EQ) != 0), eq);
     const size_t plane = L.plane;
 #pragma unroll
     for (int i = 0; i < Q; i++)
-        st_off(dst + (size_t)i * plane, n, out_code<Q, F>(L, fl, any_eq, i, Codec<F>::template store_raw<A>(fo[i], tab)));
+        st_off(dst + (size_t)i * plane, n, out_code<F>(fl, eq[i], Codec<F>::template store_raw<A>(fo[i], tab)));
 }
 
 // ------------------------------------------------------------ several cells per lane
@@ -873,12 +892,17 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
     }
     if (__any(any_special)) {
         // wall and equilibrium cells write back what they keep (whole rows)
+        bool any_eq_cell = false;
+#pragma unroll
+        for (int k = 0; k < CPL; k++) any_eq_cell |= ((fl4 >> (8 * k)) & F_EQ) != 0;
+        T eq[Q];
+        eq_codes_if<Q, F>(L, __any(any_eq_cell), eq);
 #pragma unroll
         for (int k = 0; k < CPL; k++) {
             const uint32_t fk = (fl4 >> (8 * k)) & 0xFF;
 #pragma unroll
             for (int i = 0; i < Q; i++)
-                if (special[k]) vreplace<T, CPL>(out[i], k, special_code<Q, F>(L, fk, i));
+                if (special[k]) vreplace<T, CPL>(out[i], k, (fk & F_EQ) ? eq[i] : (T)0);
         }
     }
 #pragma unroll
@@ -955,7 +979,6 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
 
     // ---- collide the K cells of this thread
     T codes[K][Q];
-    const T* eqc = (const T*)L.eq_codes;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const uint32_t xl = threadIdx.x + k * B;
@@ -966,7 +989,7 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
             for (int i = 0; i < Q; i++) codes[k][i] = Codec<F>::template store<A>((A)0, tab);
         } else if (fl & F_EQ) {
 #pragma unroll
-            for (int i = 0; i < Q; i++) codes[k][i] = ld_off(eqc, (uint32_t)i);
+            for (int i = 0; i < Q; i++) codes[k][i] = eq_code<F>(L, i);
         } else {
             A f[Q], fo[Q];
 #pragma unroll
