@@ -10,9 +10,13 @@ before timing.
 
 Prints one JSON line: MLUPs/s (10^6 cell updates per second, all cells of the
 box), the HBM roofline of the dominant kernel (algorithmic bytes per launch /
-measured launch time vs 8 TB/s), the L2 velocity error of each FP32 storage
-format against the FP64 GPU path on a 64^3 cavity after 1000 steps, and the
-FP64 CPU reference timed on the host cores on a bounded sample.
+measured launch time vs 8 TB/s, and the HBM traffic from the committed
+rocprofv3 counter summary when it was taken on the current kernel sources),
+the L2 velocity error of each FP32 storage format against the FP64 GPU path
+on a 64^3 cavity after 1000 steps, the FP64 CPU reference timed on the host
+cores on a bounded sample, and, unless switched off, the 256-lattice
+ensemble, the full-size Karman channel (1024x256x64, D3Q27) and the periodic
+256^3 boxes of the paper's performance table.
 """
 from __future__ import annotations
 
