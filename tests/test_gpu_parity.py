@@ -275,6 +275,34 @@ def test_boundaries_replaced_like_fresh_handle(lbm, orc):
             assert np.array_equal(res[0][k], res[1][k]), (cfg, k)
 
 
+def test_walls_at_group_edges(lbm, orc):
+    """Single wall cells at the edges of the 64-cell groups that mark
+    wall-adjacent wavefronts (cells 63/64, 127/128, the last cell, rows of
+    100 cells that do not start on a group), stepped in FP64 in every launch
+    kind and workgroup size: equal to the reference to 1e-13 after 4 steps."""
+    nx, ny, nz = 100, 3, 4
+    N = nx * ny * nz
+    flags = np.zeros(N, np.uint8)
+    for n in (63, 128, 191, 250, N - 1):
+        flags[n] = wl.SOLID
+    flags[300] = wl.SOLID | wl.MOVING
+    rho, u = wl.random_fields(N, seed=77)
+    ref = orc.Lattice(nx, ny, nz, q=19, tau=0.7, collision="trt", wall_u=(0.02, -0.03, 0.01), flags=flags)
+    ref.init(rho, u).step(4)
+    for cfg in (dict(mode=0, block=64), dict(mode=0, block=256), dict(mode=1, block=64),
+                dict(mode=2, block=64), dict(mode=2, block=512)):
+        with lbm.Lattices(lbm.make_params(nx, ny, nz, q=19, collision="trt", storage="fp64", arith="fp64",
+                                          tau=0.7, wall_u=(0.02, -0.03, 0.01))) as g:
+            g.set_boundaries(0, flags)
+            g.set_launch(**cfg)
+            g.set_rho_u(0, rho, u)
+            g.step(4)
+            f = g.get_ddf(0)
+        fluid = flags == 0
+        err = np.abs(f[:, fluid] - ref.f[:, fluid]).max()
+        assert err <= 1e-13 * np.abs(ref.f[:, fluid]).max(), (cfg, err)
+
+
 def test_invalid_launch_rejected(lbm):
     with lbm.Lattices(lbm.make_params(30, 4, 4, storage="fp16s")) as g:
         with pytest.raises(lbm.LbmError):
