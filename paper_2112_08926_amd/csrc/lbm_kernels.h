@@ -146,7 +146,9 @@ __device__ __forceinline__ uint32_t src_x(int i, uint32_t x, uint32_t xm, uint32
 // Element `idx` of a row/plane at a wavefront-uniform base: the byte offset
 // is formed in 32 bits so that the load/store can use a scalar 64-bit base
 // plus a 32-bit per-lane offset (no 64-bit address arithmetic per lane).
-// Every offset here is below 2^32 bytes (N * bytes per DDF < 2^32).
+// Every offset passed here is below 2^32 bytes: DDF planes (N * bytes per
+// DDF < 2^32) and byte-per-cell arrays (N < 2^31); the 4-byte-per-cell wall
+// mask goes through ld_mask.
 // The pointers are in the global address space: every buffer of the library
 // is device memory.  Saying so matters where a pointer comes from a
 // descriptor table in memory rather than a kernel argument; the compiler
@@ -159,6 +161,12 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ __forceinline__ T ld_off(const T* base, uint32_t idx) {
     return *(const LBM_GLOBAL T*)((const LBM_GLOBAL char*)base + (uint32_t)(idx * (uint32_t)sizeof(T)));
+}
+// The wall mask of cell n.  It holds 4 bytes per cell, so its byte offset can
+// pass 2^32 in lattices of 2^30 cells or more (allowed with 16-bit storage):
+// the address is formed in 64 bits.
+__device__ __forceinline__ uint32_t ld_mask(const uint32_t* mask, uint32_t n) {
+    return *(const LBM_GLOBAL uint32_t*)(mask + (size_t)n);
 }
 // New DDFs are streamed out: nontemporal stores (each element is written
 // once per step and read back only by the next step).
@@ -217,7 +225,7 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
         }
         return;
     }
-    const uint32_t m = ld_off(L.wall_mask, n);
+    const uint32_t m = ld_mask(L.wall_mask, n);
     // All Q loads first, addresses chosen by selects (no branch between the
     // loads, so they are all in flight at once) ...
 #pragma unroll
@@ -869,7 +877,7 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
             const uint32_t xk = x + k;
             const uint32_t xkm = xk == 0 ? nx - 1 : xk - 1;
             const uint32_t xkp = xk + 1 == nx ? 0 : xk + 1;
-            const uint32_t m = near[k] ? ld_off(L.wall_mask, row + xk) : 0u;
+            const uint32_t m = near[k] ? ld_mask(L.wall_mask, row + xk) : 0u;
 #pragma unroll
             for (int i = 1; i < Q; i++) {
                 if (m & (1u << i)) {
@@ -1000,7 +1008,7 @@ __device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32
                 const uint32_t x = x0 + xl;
                 const uint32_t xm = x == 0 ? nx - 1 : x - 1;
                 const uint32_t xp = x + 1 == nx ? 0 : x + 1;
-                const uint32_t m = near ? ld_off(L.wall_mask, row + x) : 0u;
+                const uint32_t m = near ? ld_mask(L.wall_mask, row + x) : 0u;
                 RowCtx rc;
                 make_rows(L, y, z, rc);
 #pragma unroll
