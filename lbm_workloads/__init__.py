@@ -218,3 +218,17 @@ def table_indices(N, seed, plane, size):
     """N seeded indices uniform in [0, size) for one direction plane of a
     full-size state (numpy PCG64 seeded with (seed, plane))."""
     return np.random.default_rng([seed, plane]).integers(0, size, N, dtype=np.uint16)
+
+
+# --------------------------------------------------------------------------
+# Karman vortex street in two dimensions (Sec. 4.3 as the paper runs it)
+# --------------------------------------------------------------------------
+def karman2d_fields(nx, ny, u0):
+    """Velocity u0 along +y on the left half x < nx/2 (the perimeter's EQ
+    cells take u0 from the lattice's EQ state), rest elsewhere: the
+    asymmetric start that triggers the instability at once."""
+    x, y, _ = cell_coords(nx, ny, 1)
+    rho = np.ones(x.size)
+    u = np.zeros((3, x.size))
+    u[1] = np.where(x < nx // 2, u0, 0.0)
+    return rho, u
