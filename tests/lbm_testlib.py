@@ -1,7 +1,7 @@
 """Helpers shared by the GPU parity tests: building matching GPU and reference
 lattices from the same seeded inputs, and comparing their states.
 
-Tolerances (derived from the arithmetic, see DESIGN.md):
+Tolerances (derived from the arithmetic):
   FP64 storage + FP64 arithmetic: relative 1e-12 after many steps (the two
     sides differ only in FMA contraction and summation rounding, ~1e-16 per op);
   FP32 arithmetic: one step differs from the FP64 reference by the FP32
