@@ -357,39 +357,63 @@ __host__ __device__ constexpr double mrt_rate_fixed(int k) {
 __host__ __device__ constexpr bool mrt_shear(int k) { return k == 9 || k == 11 || k == 13 || k == 14 || k == 15; }
 __host__ __device__ constexpr bool mrt_conserved(int k) { return k == 0 || k == 3 || k == 5 || k == 7; }
 
-// The matrix products as fold expressions over compile-time indices, so each
-// coefficient is a constant and the zero ones vanish.
-template <class A, int K, int... I>
-__device__ __forceinline__ A mrt_row(const A (&v)[19], std::integer_sequence<int, I...>) {
+// Every row is even or odd in c (rho, e, eps and the stress moments even; j,
+// q and m odd), so a direction and its opposite carry the same coefficient
+// up to the sign: the products are taken over the 9 opposite pairs, even
+// rows on the pair sums and odd rows on the pair differences, as fold
+// expressions over compile-time indices so that each coefficient is a
+// constant and the zero ones vanish.
+__host__ __device__ constexpr bool mrt_odd(int k) { return (k >= 3 && k <= 8) || k >= 16; }
+// Row K of M applied to v, given v0 = v[0], s[p] = v[2p+1] + v[2p+2] and
+// a[p] = v[2p+1] - v[2p+2].
+template <class A, int K, int... P>
+__device__ __forceinline__ A mrt_row(A v0, const A (&s)[9], const A (&a)[9], std::integer_sequence<int, P...>) {
     A acc = (A)0;
-    ((acc = mrt_m(K, I) != 0 ? fmaa((A)mrt_m(K, I), v[I], acc) : acc), ...);
+    if constexpr (!mrt_odd(K) && mrt_m(K, 0) != 0) acc = (A)mrt_m(K, 0) * v0;
+    ((acc = mrt_m(K, 2 * P + 1) != 0 ? fmaa((A)mrt_m(K, 2 * P + 1), mrt_odd(K) ? a[P] : s[P], acc) : acc), ...);
     return acc;
 }
-template <class A, int I, int... K>
+// Column entries of M^T r for direction I over the rows K of one parity.
+template <class A, int I, bool ODD, int... K>
 __device__ __forceinline__ A mrt_col(const A (&r)[19], std::integer_sequence<int, K...>) {
     A acc = (A)0;
-    ((acc = mrt_m(K, I) != 0 ? fmaa((A)mrt_m(K, I), r[K], acc) : acc), ...);
+    ((acc = (mrt_odd(K) == ODD && mrt_m(K, I) != 0) ? fmaa((A)mrt_m(K, I), r[K], acc) : acc), ...);
     return acc;
 }
-template <class A, int K>
-__device__ __forceinline__ A mrt_relax_one(A w, bool forced, const A (&d)[19], const A (&src)[19]) {
-    constexpr auto idx = std::make_integer_sequence<int, 19>{};
+// Relaxed moment K divided by |row K|^2: S_K (M d)_K, minus (1 - S_K/2)
+// (M src)_K with a body force (FORCED).
+template <class A, int K, bool FORCED>
+__device__ __forceinline__ A mrt_relax_one(A w, A d0, const A (&ds)[9], const A (&da)[9], A f0,
+                                           const A (&fs)[9], const A (&fa)[9]) {
+    constexpr auto pairs = std::make_integer_sequence<int, 9>{};
     const A sk = mrt_shear(K) ? w : (A)mrt_rate_fixed(K);
     A rk = (A)0;
-    if constexpr (!mrt_conserved(K)) rk = sk * mrt_row<A, K>(d, idx);
-    if (forced) rk = fmaa(-((A)1 - (A)0.5 * sk), mrt_row<A, K>(src, idx), rk);
+    if constexpr (!mrt_conserved(K)) rk = sk * mrt_row<A, K>(d0, ds, da, pairs);
+    if constexpr (FORCED) rk = fmaa(-((A)1 - (A)0.5 * sk), mrt_row<A, K>(f0, fs, fa, pairs), rk);
     return rk * (A)(1.0 / mrt_norm2(K));
 }
-template <class A, int... K>
-__device__ __forceinline__ void mrt_relax(A w, bool forced, const A (&d)[19], const A (&src)[19], A (&r)[19],
+template <class A, bool FORCED, int... K>
+__device__ __forceinline__ void mrt_relax(A w, const A (&d)[19], const A (&src)[19], A (&r)[19],
                                           std::integer_sequence<int, K...>) {
-    ((r[K] = mrt_relax_one<A, K>(w, forced, d, src)), ...);
+    A ds[9], da[9], fs[9], fa[9];
+#pragma unroll
+    for (int p = 0; p < 9; p++) {
+        ds[p] = d[2 * p + 1] + d[2 * p + 2];
+        da[p] = d[2 * p + 1] - d[2 * p + 2];
+        fs[p] = FORCED ? src[2 * p + 1] + src[2 * p + 2] : (A)0;
+        fa[p] = FORCED ? src[2 * p + 1] - src[2 * p + 2] : (A)0;
+    }
+    ((r[K] = mrt_relax_one<A, K, FORCED>(w, d[0], ds, da, src[0], fs, fa)), ...);
 }
-template <class A, int... I>
+// fo = f - M^T r: per pair, the even rows' sum E and the odd rows' sum O give
+// f_i - (E + O) and f_opp - (E - O).
+template <class A, int... P>
 __device__ __forceinline__ void mrt_back(const A (&f)[19], const A (&r)[19], A (&fo)[19],
-                                         std::integer_sequence<int, I...>) {
-    constexpr auto idx = std::make_integer_sequence<int, 19>{};
-    ((fo[I] = f[I] - mrt_col<A, I>(r, idx)), ...);
+                                         std::integer_sequence<int, P...>) {
+    constexpr auto rows = std::make_integer_sequence<int, 19>{};
+    fo[0] = f[0] - mrt_col<A, 0, false>(r, rows);
+    ((fo[2 * P + 1] = f[2 * P + 1] - (mrt_col<A, 2 * P + 1, false>(r, rows) + mrt_col<A, 2 * P + 1, true>(r, rows))), ...);
+    ((fo[2 * P + 2] = f[2 * P + 2] - (mrt_col<A, 2 * P + 1, false>(r, rows) - mrt_col<A, 2 * P + 1, true>(r, rows))), ...);
 }
 
 // f' = f - M^-1 [S M (f - f^eq) - (I - S/2) M S^F] with the Guo source S^F;
@@ -400,9 +424,8 @@ __device__ __forceinline__ void collide_mrt(A w, A rho, A rhom1, A C, A u3x, A u
                                             A (&fo)[19]) {
     constexpr double kSc = (double)(1u << E);
     const A sc = (A)kSc;
-    A d[19], src[19];
+    A d[19];
     d[0] = f[0] - feq0;
-    src[0] = sc * ((A)VelSet<19>::w(0) * ((A)(-3) * uF));
 #pragma unroll
     for (int i = 1; i < 19; i += 2) {
         const A wi = (A)(VelSet<19>::w(i) * kSc);
@@ -410,17 +433,27 @@ __device__ __forceinline__ void collide_mrt(A w, A rho, A rhom1, A C, A u3x, A u
         const A t = fmaa(B, B, C);
         d[i] = f[i] - fmaa(wi * rho, fmaa((A)0.5, t, B), wi * rhom1);
         d[i + 1] = f[i + 1] - fmaa(wi * rho, fmaa((A)0.5, t, -B), wi * rhom1);
-        const A wp = (A)VelSet<19>::w(i);
-        const A cF = cdot_i<19, A>(i, Fx, Fy, Fz);
-        const A cu = cdot_i<19, A>(i, ux, uy, uz);
-        const A sym = wp * ((A)9 * cu * cF - (A)3 * uF);
-        const A anti = wp * (A)3 * cF;
-        src[i] = sc * (sym + anti);
-        src[i + 1] = sc * (sym - anti);
     }
     A r[19];                                     // relaxed moments, divided by |row|^2
-    mrt_relax<A>(w, forced, d, src, r, std::make_integer_sequence<int, 19>{});
-    mrt_back<A>(f, r, fo, std::make_integer_sequence<int, 19>{});
+    if (forced) {                                // wavefront-uniform
+        A src[19];
+        src[0] = sc * ((A)VelSet<19>::w(0) * ((A)(-3) * uF));
+#pragma unroll
+        for (int i = 1; i < 19; i += 2) {
+            const A wp = (A)VelSet<19>::w(i);
+            const A cF = cdot_i<19, A>(i, Fx, Fy, Fz);
+            const A cu = cdot_i<19, A>(i, ux, uy, uz);
+            const A sym = wp * ((A)9 * cu * cF - (A)3 * uF);
+            const A anti = wp * (A)3 * cF;
+            src[i] = sc * (sym + anti);
+            src[i + 1] = sc * (sym - anti);
+        }
+        mrt_relax<A, true>(w, d, src, r, std::make_integer_sequence<int, 19>{});
+    } else {
+        const A none[19] = {};
+        mrt_relax<A, false>(w, d, none, r, std::make_integer_sequence<int, 19>{});
+    }
+    mrt_back<A>(f, r, fo, std::make_integer_sequence<int, 9>{});
 }
 
 // Computes the post-collision DDFs fo[] of one cell from the pulled f[].
