@@ -83,3 +83,23 @@ def test_codec_entry_points_reject_bad_arguments_without_device():
     # n == 0 is a no-op and touches no device
     lbm.lbm_encode("fp16c", 0, 0, 0)
     assert np.dtype(np.uint16).itemsize == 2
+
+
+@pytest.mark.parametrize("dims,storage", [((1024, 1024, 1024), "fp32"),      # N * 4 = 2^32
+                                          ((2048, 1024, 1024), "fp16s"),     # N = 2^31
+                                          ((1024, 1024, 512), "fp64")])      # N * 8 = 2^32
+def test_create_rejects_lattices_past_the_offset_limits_without_device(dims, storage):
+    """One past the largest lattices the 32-bit in-plane offsets allow (the
+    largest ones themselves are stepped by the GPU tests)."""
+    import paper_2112_08926_amd as lbm
+    arith = "fp64" if storage == "fp64" else "fp32"
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create(lbm.make_params(*dims, storage=storage, arith=arith))
+    assert ei.value.code == -1 and "32-bit" in str(ei.value)
+
+
+def test_create_rejects_an_empty_ensemble_without_device():
+    import paper_2112_08926_amd as lbm
+    with pytest.raises(lbm.LbmError) as ei:
+        lbm.lbm_create([])
+    assert ei.value.code == -1
