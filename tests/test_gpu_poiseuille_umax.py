@@ -3,9 +3,11 @@
 R = 31 and R = 63): D3Q19 SRT, Guo force, mid-grid bounce-back, a periodic
 slab 4 cells long, run for 3 R^2 / nu steps.  At fixed Re and R,
 u_max = Re nu / (2 R), so the sweep runs over tau (nu = (tau - 1/2) / 3) and
-tau = 1 marks u_max = Re / (12 R).  R = 31 runs Re = 1, 10, 100; R = 63 runs
-Re = 10, 100 (at Re <= 1 every 16-bit point of that panel has failed).  The
-paper states, and the bars below check with margins:
+tau = 1 marks u_max = Re / (12 R).  Both radii run Re = 1, 10, 100 (at
+Re = 0.1, the paper's fourth curve, FP16C has failed up to tau = 1.5 and the
+comparisons below do not apply; the paper states the FP16C advantage for the
+higher Reynolds numbers).  Each radius is swept the first time a test asks
+for it.  The paper states, and the bars below check with margins:
 
 * the error minimum stays close to tau = 1 (here, for both radii: FP64's
   minimum lies at tau in [0.9, 1.6], i.e. u_max within a factor 2 of its
@@ -18,16 +20,16 @@ paper states, and the bars below check with margins:
   u_max = 2.7e-4, FP16S stays within 10 % of FP64 while FP16C has failed,
   E > 0.5);
 * without DDF shifting the 16-bit formats become very inaccurate (here: for
-  Re <= 10 every point at least 3x worse than shifted (where shifted has not
-  itself failed), and failed, E > 0.5, for tau <= 1; at Re = 100 the
+  Re <= 10 every unshifted point has failed, E > 0.5, or is at least 3x
+  worse than shifted, and failed for tau <= 1; at Re = 100 the
   unshifted/shifted error ratio has a geometric mean over the sweep of at
   least 2, though single points come close to 1); FP32 benefits from
   shifting at low velocities (unshifted FP32 has failed at R = 31, Re = 1,
-  tau = 0.55, and is over 10x worse than shifted at R = 63, Re = 10,
-  tau = 0.6) and FP64 does not notice it (within 1 % everywhere); shifted
-  FP32 matches FP64 within 8 % at every point of R = 31 and within 25 % at
-  R = 63, where 358 000 steps at tau = 0.6 leave it up to 20 % off (below
-  FP64's error there, not above)."""
+  tau = 0.55, and at R = 63, Re = 1, tau = 0.6, and is over 10x worse than
+  shifted at R = 63, Re = 10, tau = 0.6) and FP64 does not notice it
+  (within 1 % everywhere); shifted FP32 matches FP64 within 8 % at every
+  point of R = 31 and within 25 % at R = 63, where 358 000 steps at
+  tau = 0.6 leave it up to 20 % off (below FP64's error there, not above)."""
 import math
 
 import pytest
@@ -39,7 +41,7 @@ pytestmark = pytest.mark.gpu
 
 NX = 4
 SWEEPS = {31: ((1.0, 10.0, 100.0), (0.55, 0.6, 0.75, 0.93, 1.0, 1.25, 1.5, 2.5)),
-          63: ((10.0, 100.0), (0.6, 0.75, 1.0, 1.25, 1.5, 2.5))}
+          63: ((1.0, 10.0, 100.0), (0.6, 0.75, 1.0, 1.25, 1.5, 2.5))}
 POINTS = [(R, Re) for R, (res, _) in SWEEPS.items() for Re in res]
 FP32_BAR = {31: 0.08, 63: 0.25}
 FORMATS = ("fp64", "fp32", "fp16s", "fp16c")
@@ -58,12 +60,10 @@ def u_max(R, Re, tau):
     return Re * (tau - 0.5) / 3.0 / (2 * R)
 
 
-@pytest.fixture(scope="module")
-def sweep(lbm):
-    out = {}
-    for R, Re in POINTS:
-        ny = nz = 2 * (R + 1)
-        flags = wl.poiseuille_flags(NX, ny, nz, R)
+def run_panel(lbm, R, out):
+    ny = nz = 2 * (R + 1)
+    flags = wl.poiseuille_flags(NX, ny, nz, R)
+    for Re in SWEEPS[R][0]:
         for tau in SWEEPS[R][1]:
             nu = (tau - 0.5) / 3.0
             u = u_max(R, Re, tau)
@@ -82,7 +82,26 @@ def sweep(lbm):
                         out[(R, Re, tau, fmt, unshifted)] = g.diagnostics(0, u_ref)["l2_error"]
             say(f"R={R} Re={Re} tau={tau} u_max={u:.2e}: " +
                 " ".join(f"{f}{'*' if s else ''}={out[(R, Re, tau, f, s)]:.2e}" for f in FORMATS for s in (False, True)))
-    return out
+
+
+class Panels(dict):
+    """Errors keyed by (R, Re, tau, format, unshifted); a radius is swept on
+    its first lookup."""
+
+    def __init__(self, lbm):
+        super().__init__()
+        self.lbm = lbm
+
+    def __missing__(self, key):
+        if any(k[0] == key[0] for k in self):
+            raise KeyError(key)
+        run_panel(self.lbm, key[0], self)
+        return self[key]
+
+
+@pytest.fixture(scope="module")
+def sweep(lbm):
+    return Panels(lbm)
 
 
 @pytest.mark.parametrize("R,Re", POINTS)
@@ -121,8 +140,8 @@ def test_shifting(sweep, R, Re):
         for fmt in ("fp16s", "fp16c"):
             ratio = sweep[(R, Re, t, fmt, True)] / sweep[(R, Re, t, fmt, False)]
             log_ratio[fmt].append(math.log(ratio))
-            if Re <= 10:         # unless the shifted run has itself failed (tiny DDFs)
-                assert ratio > 3.0 or sweep[(R, Re, t, fmt, False)] > 0.5, (R, Re, t, fmt, ratio)
+            if Re <= 10:
+                assert ratio > 3.0 or sweep[(R, Re, t, fmt, True)] > 0.5, (R, Re, t, fmt, ratio)
                 if t <= 1.0:
                     assert sweep[(R, Re, t, fmt, True)] > 0.5, (R, Re, t, fmt)
     for fmt, lr in log_ratio.items():
@@ -131,4 +150,5 @@ def test_shifting(sweep, R, Re):
 
 def test_unshifted_fp32_worse_at_low_velocity(sweep):
     assert sweep[(31, 1.0, 0.55, "fp32", True)] > 0.5
+    assert sweep[(63, 1.0, 0.6, "fp32", True)] > 0.5
     assert sweep[(63, 10.0, 0.6, "fp32", True)] > 10 * sweep[(63, 10.0, 0.6, "fp32", False)]
