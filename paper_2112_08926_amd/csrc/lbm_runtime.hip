@@ -70,7 +70,11 @@ static lbm_status device_table(int storage, const EncEntry** out) {
             return fail(LBM_EDEVICE, "encoder table of format %d: %s", storage, why.c_str());
         EncEntry* d = nullptr;
         HIP_TRY(hipMalloc(&d, sizeof host));
-        HIP_TRY(hipMemcpy(d, host, sizeof host, hipMemcpyHostToDevice));
+        const hipError_t e = hipMemcpy(d, host, sizeof host, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return fail(LBM_EDEVICE, "encoder table upload: %s", hipGetErrorString(e));
+        }
         g_tables.dev[storage] = d;
     }
     *out = g_tables.dev[storage];
@@ -689,19 +693,17 @@ extern "C" lbm_status lbm_set_rho_u(lbm_handle* h, int32_t k, const double* rho,
     Lattice& L = h->lats[k];
     double* d_rho = nullptr;
     double* d_u = nullptr;
-    if (rho) {
-        if (hipMalloc(&d_rho, L.N * sizeof(double)) != hipSuccess) return fail(LBM_ENOMEM, "rho upload buffer");
-        HIP_TRY(hipMemcpyAsync(d_rho, rho, L.N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    if ((rho && hipMalloc(&d_rho, L.N * sizeof(double)) != hipSuccess) ||
+        (u && hipMalloc(&d_u, 3 * L.N * sizeof(double)) != hipSuccess)) {
+        (void)hipFree(d_rho);
+        return fail(LBM_ENOMEM, "rho/u upload buffers");
     }
-    if (u) {
-        if (hipMalloc(&d_u, 3 * L.N * sizeof(double)) != hipSuccess) {
-            (void)hipFree(d_rho);
-            return fail(LBM_ENOMEM, "u upload buffer");
-        }
-        HIP_TRY(hipMemcpyAsync(d_u, u, 3 * L.N * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    }
-    st = run_init(h, L, d_rho, d_u);
-    hipError_t e = hipStreamSynchronize(h->stream);
+    hipError_t e = hipSuccess;
+    if (rho) e = hipMemcpyAsync(d_rho, rho, L.N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(d_u, u, 3 * L.N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    st = e == hipSuccess ? run_init(h, L, d_rho, d_u) : LBM_OK;
+    const hipError_t es = hipStreamSynchronize(h->stream);    // the uploads read the caller's buffers
+    if (e == hipSuccess) e = es;
     (void)hipFree(d_rho);
     (void)hipFree(d_u);
     if (st != LBM_OK) return st;
