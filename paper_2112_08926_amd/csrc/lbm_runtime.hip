@@ -897,8 +897,7 @@ extern "C" lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launc
     lbm_launch best_cfg = keep;
     for (const lbm_launch& c : cands) {
         h->launch = c;
-        lbm_status st = rebuild_tiles(h);
-        if (st != LBM_OK) break;
+        if (rebuild_tiles(h) != LBM_OK) continue;      // e.g. no memory for its tile tables: skip it
         // warm-up, then the better of two timed runs (one run alone is
         // noisy enough to flip close candidates); always reading the
         // current buffer
