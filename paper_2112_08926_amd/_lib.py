@@ -160,6 +160,15 @@ def _host_ptr(a: np.ndarray | None):
     return None if a is None else a.ctypes.data_as(_P)
 
 
+def _sized(a, dtype, n: int, what: str) -> np.ndarray:
+    """C-ordered copy (or view) of `a` as `dtype`; the library reads exactly
+    n elements from it, so any other size is refused here."""
+    c = np.ascontiguousarray(a, dtype=dtype)
+    if c.size != n:
+        raise ValueError(f"{what}: {c.size} elements, the lattice needs {n}")
+    return c
+
+
 def make_params(nx, ny, nz, q=19, collision="srt", storage="fp32", arith="fp32", tau=0.6,
                 trt_magic=0.25, force=(0.0, 0.0, 0.0), wall_u=(0.0, 0.0, 0.0), eq_rho=1.0,
                 eq_u=(0.0, 0.0, 0.0), unshifted=False) -> LbmParams:
@@ -224,7 +233,8 @@ def lbm_set_ddf(h, lattice: int, codes: np.ndarray):
 
 
 def lbm_get_ddf(h, lattice: int, out: np.ndarray):
-    assert out.flags.c_contiguous
+    if not out.flags.c_contiguous:
+        raise ValueError("out must be C-contiguous")
     _check(library().lbm_get_ddf(h, lattice, _host_ptr(out)))
     return out
 
@@ -306,10 +316,12 @@ class Lattices:
         return _DTYPE.get(self.storage, np.uint16)
 
     def set_boundaries(self, k: int, flags):
-        lbm_set_boundaries(self.h, k, flags)
+        lbm_set_boundaries(self.h, k, _sized(flags, np.uint8, self.N(k), "flags"))
 
     def set_rho_u(self, k: int, rho=None, u=None):
-        lbm_set_rho_u(self.h, k, rho, u)
+        n = self.N(k)
+        lbm_set_rho_u(self.h, k, None if rho is None else _sized(rho, np.float64, n, "rho"),
+                      None if u is None else _sized(u, np.float64, 3 * n, "u"))
 
     def step(self, n: int = 1):
         lbm_step(self.h, n)
@@ -322,11 +334,11 @@ class Lattices:
         return lbm_get_ddf(self.h, k, out)
 
     def set_ddf(self, k: int, codes):
-        c = np.ascontiguousarray(codes, dtype=self.ddf_dtype()).reshape(self.q, self.N(k))
-        lbm_set_ddf(self.h, k, c)
+        lbm_set_ddf(self.h, k, _sized(codes, self.ddf_dtype(), self.q * self.N(k), "codes"))
 
     def diagnostics(self, k: int = 0, u_ref=None) -> dict:
-        return lbm_diagnostics(self.h, k, u_ref).as_dict()
+        ref = None if u_ref is None else _sized(u_ref, np.float64, 3 * self.N(k), "u_ref")
+        return lbm_diagnostics(self.h, k, ref).as_dict()
 
     def set_launch(self, mode=None, block=None, cells_per_lane=None, staged=None, persistent=None,
                    graph_steps=None):
