@@ -155,6 +155,48 @@ def test_batched_equals_per_lattice_and_graph(lbm, orc):
             assert np.array_equal(a, b), name
 
 
+def test_graph_replays_match_eager(lbm):
+    """A captured graph replayed five times in a row, with the handle's own
+    eager work (moments, FP64 reductions, host copies) and synchronisations
+    between the replays: after every replay the state is bit-identical to
+    the same steps launched one by one.  A single cavity (walls, moving lid)
+    and a persistent batched ensemble."""
+    import torch
+    n = 40
+    cav = [lbm.make_params(n, 24, 16, q=19, collision="trt", storage="fp16s", tau=0.58, wall_u=(0.0, 0.08, 0.0))]
+    specs = wl.ensemble_specs(count=4, seed=7, lo=16, hi=40)
+    ens = [lbm.make_params(s["nx"], s["ny"], s["nz"], storage="fp16c", tau=s["tau"], force=s["force"]) for s in specs]
+    cases = [("cavity", cav, [(wl.cavity_flags(n, 24, 16), None, None)], dict(mode=0, block=256), 2),
+             ("ensemble", ens, [wl.ensemble_member_inputs(s) for s in specs], dict(mode=1, block=128, persistent=2), 4)]
+    for name, params, inputs, cfg, K in cases:
+        handles = []
+        for graph_steps in (0, K):
+            g = lbm.Lattices(params)
+            for k, (flags, rho, u) in enumerate(inputs):
+                g.set_boundaries(k, flags)
+                if rho is not None:
+                    g.set_rho_u(k, rho, u)
+            g.set_launch(graph_steps=graph_steps, **cfg)
+            handles.append(g)
+        eager, graph = handles
+        try:
+            for replay in range(5):
+                say(f"graph replay {name} {replay}")
+                graph.step(K)
+                eager.step(K)
+                d = graph.diagnostics(0)
+                graph.get_rho_u(len(params) - 1)
+                torch.cuda.synchronize()
+                assert d["nonfinite_cells"] == 0 and d["step"] == (replay + 1) * K
+                for k in range(len(params)):
+                    assert np.array_equal(graph.get_ddf(k), eager.get_ddf(k)), (name, replay, k)
+            moved = graph.get_ddf(0).astype(np.int64)
+            assert np.count_nonzero(moved) > 0, name
+        finally:
+            for g in handles:
+                g.close()
+
+
 def test_diagnostics_match_reference(lbm, orc):
     """FP64 Poiseuille-like channel with walls and a force: mass, momentum,
     kinetic energy, L2 error and momentum-exchange force against the
