@@ -172,7 +172,12 @@ lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, void* stream
 /* Set the cell flags of one lattice from host uint8[N] (bits LBM_FLAG_*;
  * MOVING without SOLID, and EQ with SOLID, are LBM_EINVAL), then
  * re-initialise that lattice to rest with EQ cells at their equilibrium.
- * Wall cells hold zero DDFs. */
+ * Wall cells hold zero DDFs.  The flags are what the paper's kernel reads
+ * per cell and per neighbour (its flag checks before streaming); the
+ * near-wall marks and masks the step uses are derived from them here, on
+ * the device.  Synchronises.  Errors: LBM_EINVAL (NULL handle or flags,
+ * lattice out of range, bad flag bits), LBM_ENOMEM (staging buffer),
+ * LBM_EDEVICE. */
 lbm_status lbm_set_boundaries(lbm_handle* h, int32_t lattice, const uint8_t* flags);
 
 /* Initialise one lattice's DDFs to the equilibrium of host fields rho[N] and
@@ -181,13 +186,19 @@ lbm_status lbm_set_boundaries(lbm_handle* h, int32_t lattice, const uint8_t* fla
  * cells zero.  Resets the step counter of the handle. */
 lbm_status lbm_set_rho_u(lbm_handle* h, int32_t lattice, const double* rho, const double* u);
 
-/* Advance every lattice by n_steps >= 0 time steps (asynchronous). */
+/* Advance every lattice by n_steps >= 0 time steps of the fused pull
+ * stream-collide update (the appendix "LBM equations in a nutshell", with
+ * DDF shifting of Sec. 2.2), alternating the two DDF buffers.  Asynchronous.
+ * Errors: LBM_EINVAL (NULL handle, n_steps < 0), LBM_EDEVICE (a launch or
+ * the graph capture failed; steps already enqueued stay enqueued). */
 lbm_status lbm_step(lbm_handle* h, int64_t n_steps);
 
 /* Density and velocity of the current state (what the next step sees after
  * streaming; velocity includes half the body force, not clamped).  SOLID
  * cells report rho = 1 and the wall velocity, EQ cells their own moments.
- * rho: host double[N] or NULL; u: host double[3*N] or NULL.  Synchronises. */
+ * rho: host double[N] or NULL; u: host double[3*N] or NULL.  Synchronises.
+ * Errors: LBM_EINVAL (NULL handle, lattice out of range), LBM_ENOMEM
+ * (device scratch of 4*N doubles), LBM_EDEVICE. */
 lbm_status lbm_get_rho_u(lbm_handle* h, int32_t lattice, double* rho, double* u);
 
 /* Raw DDF codes of the current state: host buffer of q*N elements of the
@@ -198,15 +209,21 @@ lbm_status lbm_get_rho_u(lbm_handle* h, int32_t lattice, double* rho, double* u)
  * into EQ cells (what lbm_set_rho_u puts there), so codes set into those
  * cells other than these last until the next step: EQ codes are streamed
  * to the neighbours once, SOLID codes are never read. */
+/* Errors: LBM_EINVAL (NULL handle or host, lattice out of range),
+ * LBM_EDEVICE. */
 lbm_status lbm_set_ddf(lbm_handle* h, int32_t lattice, const void* host);
 lbm_status lbm_get_ddf(lbm_handle* h, int32_t lattice, void* host);
 
 /* FP64 diagnostics of one lattice.  u_ref: NULL or host double[3*N] for the
  * L2 error.  Fills *out; returns LBM_ENONFINITE (after filling) if
- * out->nonfinite_cells > 0.  Synchronises. */
+ * out->nonfinite_cells > 0.  Synchronises.  Other errors: LBM_EINVAL (NULL
+ * handle or out, lattice out of range), LBM_ENOMEM (device copy of u_ref),
+ * LBM_EDEVICE. */
 lbm_status lbm_diagnostics(lbm_handle* h, int32_t lattice, const double* u_ref, lbm_diag* out);
 
-/* Launch configuration (see lbm_launch); invalid values are LBM_EINVAL. */
+/* Launch configuration (see lbm_launch); invalid values are LBM_EINVAL and
+ * leave the current configuration in place.  Setting one drops a captured
+ * graph (it is captured again at the next lbm_step). */
 lbm_status lbm_set_launch(lbm_handle* h, const lbm_launch* cfg);
 lbm_status lbm_get_launch(lbm_handle* h, lbm_launch* cfg);
 
@@ -214,13 +231,22 @@ lbm_status lbm_get_launch(lbm_handle* h, lbm_launch* cfg);
  * launch, then the better of two runs of trial_steps launches, each reading
  * the current state and writing the other buffer, so the state is left
  * unchanged), keep the fastest (ties within 0.5 % go to the candidate tried
- * first, the smaller workgroup) and return it.  The graph setting of the
- * current configuration is kept. */
+ * first, the smaller workgroup) and return it (best may be NULL).  The graph
+ * setting of the current configuration is kept; candidates the handle's
+ * lattices do not admit are skipped.  Errors: LBM_EINVAL (NULL handle,
+ * trial_steps < 1), LBM_EDEVICE (a trial launch failed; the previous
+ * configuration is restored). */
 lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launch* best);
 
+/* Sizes, device memory and step counter of a handle.  LBM_EINVAL for NULL. */
 lbm_status lbm_info_get(lbm_handle* h, lbm_info* out);
+/* Wait for all work enqueued on the handle's stream.  LBM_EINVAL for NULL,
+ * LBM_EDEVICE if the stream reports an error. */
 lbm_status lbm_synchronize(lbm_handle* h);
+/* Wait for the handle's stream, then free everything it holds (NULL: no-op). */
 void lbm_destroy(lbm_handle* h);
+/* Message of the last failure in the calling thread; never NULL (empty
+ * before any failure); valid until that thread's next library call. */
 const char* lbm_last_error(void);
 
 /* Storage codecs on device arrays (Sec. 3): encode n floats into n codes of
