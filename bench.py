@@ -331,8 +331,8 @@ def main():
                     help="skip the periodic-box runs (the paper's performance workload, other velocity sets)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py: the step runs on one GPU; --gpus {args.gpus} is not supported (splitting the "
+              "lattice into z slabs with a halo exchange per step is not implemented)", file=sys.stderr)
         return 2
     import torch
     if not torch.cuda.is_available():
