@@ -20,3 +20,15 @@ def test_kernel_source_hash_is_stable_hex():
     h = bench.kernel_source_hash()
     assert len(h) == 16 and all(c in "0123456789abcdef" for c in h)
     assert h == bench.kernel_source_hash()
+
+
+def test_committed_traffic_matches_the_current_kernels(monkeypatch):
+    """The committed counter summary is used while it names the current
+    kernel sources, and dropped (traffic null) once they differ."""
+    sys.path.insert(0, ROOT)
+    import bench
+    t = bench.traffic_from_profile("fp16s")
+    assert t is not None and 10.0e9 < t < 12.0e9        # 512^3 FP16S: 10.33 GB algorithmic per step
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.traffic_from_profile("fp16s") is None
+    assert bench.traffic_from_profile("fp32") is None   # no summary for that format
