@@ -11,7 +11,13 @@ Parity status per function (each is pinned by ``tests/test_oracle_*.py``):
   decode / encode (all six 16-bit formats)   pinned: Table 2, Fig. 2, IEEE via numpy
   velset / equilibrium                       pinned: moment identities, Table 1
   step (pull, bounce-back, SRT, TRT, Guo)    pinned: streaming, conservation, closed forms
+  velocity clamp (incl. NaN)                 pinned: clamped moments at omega = 1, rho = 0 cell
+  moving-wall bounce-back                    pinned: plane Couette closed form (exact)
+  Guo source                                 pinned: its zeroth, first and second moments
+  non-finite count before the clamp          pinned: rho = 0 and NaN cells
   moments / diagnostics                      pinned: closed forms, brute-force sums
+``tests/test_oracle_mutations.py`` plants one plausible mistake at a time in
+a copy of lbm_oracle.c and checks that these pins catch every one.
 """
 from __future__ import annotations
 
@@ -24,6 +30,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+# The mutation test (tests/test_oracle_mutations.py) points this at a build of
+# a deliberately broken copy of lbm_oracle.c to show that the pins catch it.
+_SO = os.environ.get("LBM_ORACLE_SO", _SO)
 
 FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "fp16s": 3, "fp16c": 4,
            "p16_0s": 5, "p16_1s": 6, "p16_2c": 7}
@@ -57,6 +66,7 @@ def lib():
         L.oracle_decode.argtypes = [ctypes.c_int, ctypes.c_uint32]
         L.oracle_encode.restype = ctypes.c_uint32
         L.oracle_encode.argtypes = [ctypes.c_int, ctypes.c_float]
+        L.oracle_step.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -195,6 +205,7 @@ class Lattice:
                       else np.ascontiguousarray(flags, dtype=np.uint8).reshape(self.N))
         self.f = np.zeros((self.q, self.N), dtype=np.float64)
         self.t = 0
+        self.nonfinite_updates = 0
 
     @property
     def f(self) -> np.ndarray:
@@ -217,15 +228,19 @@ class Lattice:
                           _ptr(u, ctypes.c_double), _ptr(self.flags, ctypes.c_uint8),
                           _ptr(self.f, ctypes.c_double))
         self.t = 0
+        self.nonfinite_updates = 0
         return self
 
     def step(self, n=1):
+        """n time steps; ``nonfinite_updates`` accumulates the fluid cells
+        whose density or velocity before the clamp was not finite."""
         out = np.empty_like(self.f)
         for _ in range(int(n)):
             rc = lib().oracle_step(ctypes.byref(self.p), _ptr(self.f, ctypes.c_double),
                                    _ptr(out, ctypes.c_double), _ptr(self.flags, ctypes.c_uint8))
-            if rc != 0:
+            if rc < 0:
                 raise RuntimeError("oracle_step failed")
+            self.nonfinite_updates += int(rc)
             self.f, out = out, self.f
             self.t += 1
         return self

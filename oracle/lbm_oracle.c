@@ -491,10 +491,19 @@ static void collide_mrt(const oracle_lattice *L, const double *fi, const double 
     }
 }
 
-static void collide_cell(const oracle_lattice *L, const double *fi, double *fo)
+/* Collides one cell; returns 1 if its density or a velocity component, as
+ * computed from the pulled DDFs before the clamp, is not finite (a blow-up
+ * that the clamp and the saturating 16-bit encoders would otherwise hide),
+ * else 0.
+ * The clamp is the listing's OpenCL clamp(u, -c, c), which that language
+ * defines as fmin(fmax(u, -c), c); fmin and fmax return the other operand
+ * when one is NaN, so a NaN component becomes -c.  C's fmin/fmax have the
+ * same rule. */
+static int collide_cell(const oracle_lattice *L, const double *fi, double *fo)
 {
     double rho, u[3], feq[27];
     fields(L, fi, &rho, u);
+    const int bad = !(isfinite(rho) && isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]));
     const double cs = 1.0 / sqrt(3.0);           /* lattice speed of sound */
     for (int a = 0; a < 3; a++) u[a] = fmin(fmax(u[a], -cs), cs);
     oracle_equilibrium(L->q, L->shifted, rho, u, feq);
@@ -538,21 +547,25 @@ static void collide_cell(const oracle_lattice *L, const double *fi, double *fo)
             }
         }
     }
+    return bad;
 }
 
 /* One time step fin -> fout, both [q][N] with cell index n = x + (y + z ny) nx.
  * Wall (SOLID) cells are skipped as in Listing 2 and keep their content;
  * READING for equilibrium (EQ) cells (only cited): they hold the equilibrium
- * of their fixed density and velocity and are not updated either. */
-int oracle_step(const oracle_lattice *L, const double *fin, double *fout, const uint8_t *flags)
+ * of their fixed density and velocity and are not updated either.
+ * Returns -1 for an unsupported lattice, else the number of fluid cells
+ * whose density or velocity before the clamp was not finite. */
+int64_t oracle_step(const oracle_lattice *L, const double *fin, double *fout, const uint8_t *flags)
 {
     if (!valid_q(L->q)) return -1;
     if (L->collision == 2 && L->q != 19) return -1;     /* the MRT basis is D3Q19's */
     const int64_t N = (int64_t)L->nx * L->ny * L->nz;
     if (L->storage >= OF_FP16) build_table(L->storage);   /* before the threads start */
+    int64_t nonfinite = 0;
 #ifdef _OPENMP
     const int nt = L->nthreads > 0 ? L->nthreads : 0;
-#pragma omp parallel for schedule(static) num_threads(nt > 0 ? nt : omp_get_max_threads())
+#pragma omp parallel for schedule(static) num_threads(nt > 0 ? nt : omp_get_max_threads()) reduction(+ : nonfinite)
 #endif
     for (int z = 0; z < L->nz; z++) {
         double fi[27], fo[27];
@@ -564,12 +577,12 @@ int oracle_step(const oracle_lattice *L, const double *fin, double *fout, const 
                     continue;
                 }
                 pull(L, fin, flags, x, y, z, fi);
-                collide_cell(L, fi, fo);
+                nonfinite += collide_cell(L, fi, fo);
                 for (int i = 0; i < L->q; i++)
                     fout[(int64_t)i * N + n] = stored_value(L->storage, fo[i]);
             }
     }
-    return 0;
+    return nonfinite;
 }
 
 /* Density and velocity the next step would see at every cell: pull, then

@@ -415,3 +415,123 @@ def test_mrt_shear_viscosity_from_taylor_green_decay(orc):
         rates.append(rate)
         assert rate / (4 * nu * k * k) == pytest.approx(1.0, abs=1e-2)
     assert rates[0] == pytest.approx(rates[1], rel=2e-3)
+
+
+# ---------------------------------------------------------------- clamp, moving wall, Guo
+def _cell_moments(c, f, shifted=True):
+    """rho and u of stored DDFs f[q] of one cell, from their sums."""
+    rho = f.sum() + (1.0 if shifted else 0.0)
+    return rho, (c.T.astype(float) @ f) / rho
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("collision", ["srt", "trt"])
+def test_clamp_limits_velocity_to_speed_of_sound(orc, q, collision):
+    """The kernel listing clamps each velocity component to [-c, c],
+    c = 1/sqrt(3).  A single periodic cell (every neighbour is itself) whose
+    DDFs carry rho = 1 and j = (0.9, -0.9, 0.9): at omega = 1 the stored DDFs
+    are the equilibrium of the clamped velocity, so their own moments give
+    rho = 1 and u = (c, -c, c), although the pulled velocity was 0.9."""
+    c, _, _ = orc.velset(q)
+    cs = 1.0 / math.sqrt(3.0)
+    lat = orc.Lattice(1, 1, 1, q=q, omega=1.0, omega_minus=1.0, collision=collision)
+    f = np.zeros(q)
+    f[1], f[2] = 0.45, -0.45                 # +x / -x: j_x = 0.9, sum 0
+    f[3], f[4] = -0.45, 0.45                 # +y / -y: j_y = -0.9
+    f[5], f[6] = 0.45, -0.45                 # +z / -z: j_z = 0.9
+    lat.f = f[:, None]
+    rho_in, u_in = _cell_moments(c, f)
+    assert rho_in == 1.0 and np.allclose(u_in, [0.9, -0.9, 0.9], rtol=1e-15)
+    lat.step()
+    rho, u = _cell_moments(c, lat.f[:, 0])
+    assert rho == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose(u, [cs, -cs, cs], rtol=0, atol=1e-15)
+    assert lat.nonfinite_updates == 0
+    # below the limit the clamp does nothing: the same cell with j/4
+    lat.f = (f / 4.0)[:, None]
+    lat.step()
+    assert np.allclose(_cell_moments(c, lat.f[:, 0])[1], [0.225, -0.225, 0.225], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("collision", ["srt", "trt", "mrt"])
+def test_zero_density_is_counted_and_stays_finite(orc, q, collision):
+    """A cell whose pulled DDFs give rho = 0 and j = 0 has the velocity 0/0,
+    not finite before the clamp: the step counts it.  The listing's OpenCL
+    clamp is fmin(fmax(u, -c), c), which maps NaN to a finite value, and
+    the equilibrium at rho = 0 is -w_i whatever that value is, so at
+    omega = 1 the cell stores -w_i exactly and stays finite (a blow-up the
+    stored state alone would not show)."""
+    if collision == "mrt" and q != 19:
+        pytest.skip("MRT is D3Q19 only")
+    _, w, _ = orc.velset(q)
+    lat = orc.Lattice(1, 1, 1, q=q, omega=1.0, omega_minus=1.0, collision=collision,
+                      rates=np.ones(19) if collision == "mrt" else None)
+    f = np.zeros(q)
+    f[0] = -1.0                              # shifted: rho = sum f + 1 = 0, j = 0
+    lat.f = f[:, None]
+    lat.step()
+    assert lat.nonfinite_updates == 1
+    assert np.all(np.isfinite(lat.f))
+    assert np.allclose(lat.f[:, 0], -w, rtol=0, atol=1e-15)
+    # the same with a non-finite DDF: counted, and the stored values are NaN
+    lat.f = np.full((q, 1), np.nan)
+    lat.step()
+    assert lat.nonfinite_updates == 2 and np.isnan(lat.f).all()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("collision", ["srt", "trt"])
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.7])
+def test_couette_between_resting_and_moving_wall(orc, q, collision, tau):
+    """Plane Couette flow: a resting wall at z = 0 and a wall moving with
+    U along x at z = nz-1 (bounce-back with the 6 w_i c_i.u_w term off the
+    moving wall, rho_w = 1), periodic in x and y.  The steady solution is
+    the linear profile u_x = U (z - 1/2) / (nz - 2) with the walls half a
+    cell outside the fluid, which mid-grid bounce-back reproduces exactly
+    for any tau; u_y = u_z = 0 and rho = 1.  A wrong sign or factor of the
+    moving-wall term changes the slope."""
+    nz, U = 10, 0.01
+    flags = np.zeros(nz, np.uint8)
+    flags[0] = wl.SOLID
+    flags[nz - 1] = wl.SOLID | wl.MOVING
+    lat = orc.Lattice(1, 1, nz, q=q, tau=tau, collision=collision, wall_u=(U, 0.0, 0.0), flags=flags).init()
+    lat.step(20000)
+    rho, u = lat.moments()
+    z = np.arange(1, nz - 1)
+    assert np.abs(u[0, 1:-1] - U * (z - 0.5) / (nz - 2)).max() <= 1e-10 * U
+    assert np.abs(u[1:, 1:-1]).max() <= 1e-14 * U
+    assert np.abs(rho[1:-1] - 1.0).max() <= 1e-14
+
+
+@pytest.mark.parametrize("q", [9, 15, 19, 27])
+def test_guo_source_moments(orc, q):
+    """The Guo source S_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i].F has zeroth
+    moment 0, first moment F and second moment u F + F u (the moments that
+    make the forcing second-order accurate).  At omega = 1 the SRT step
+    stores feq(rho, u) + S_i / 2 with u = (j + F/2)/rho, so S is recovered
+    from one step of a single periodic cell and its three moments are
+    checked against these identities (a wrong coefficient in either part
+    of S changes one of them)."""
+    c, _, _ = orc.velset(q)
+    cf = c.astype(np.float64)
+    F = np.array([3e-4, -2e-4, 0.0 if q == 9 else 1e-4])
+    rng = np.random.default_rng(123 + q)
+    rho0, u0 = 1.01, np.array([0.03, -0.02, 0.0 if q == 9 else 0.04])
+    f = orc.equilibrium(q, rho0, u0) + 1e-3 * rng.standard_normal(q)
+    if q == 9:
+        # keep the D2Q9 cell in the plane: no z component to leave
+        f = f.copy()
+    lat = orc.Lattice(1, 1, 1, q=q, omega=1.0, collision="srt", force=tuple(F))
+    lat.f = f[:, None]
+    rho = f.sum() + 1.0
+    u = (cf.T @ f + 0.5 * F) / rho
+    lat.step()
+    S = 2.0 * (lat.f[:, 0] - orc.equilibrium(q, rho, u))
+    assert abs(S.sum()) <= 1e-15
+    assert np.allclose(cf.T @ S, F, rtol=1e-12, atol=1e-18)
+    second = np.einsum("i,ia,ib->ab", S, cf, cf)
+    expect = np.outer(u, F) + np.outer(F, u)
+    if q == 9:
+        second, expect = second[:2, :2], expect[:2, :2]
+    assert np.allclose(second, expect, rtol=1e-10, atol=1e-17)
