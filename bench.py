@@ -85,13 +85,58 @@ def time_steps(g, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def measure_format(storage, n, steps, warmup):
+def diag_cost(g, flags, q, storage, every, steps):
+    """Cost of the FP64 diagnostics (lbm_diagnostics: both reduction passes
+    and the copy of the results to the host, which synchronises): the time
+    of one call measured with events on the handle's stream, its algorithmic
+    bytes (Q b + 1 per fluid cell, the flag byte per other cell) per second,
+    and the wall-clock overhead per step of calling it every `every` steps
+    over `steps` steps, against the same steps without it."""
+    import torch
+    stream = g.stream
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(5):
+        e0.record(stream)
+        d = g.diagnostics(0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    N = flags.size
+    n_fluid = int(np.count_nonzero(flags == 0))
+    alg = n_fluid * (q * ddf_bytes(storage) + 1) + (N - n_fluid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps)
+    g.synchronize()
+    plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps // every):
+        g.step(every)
+        d = g.diagnostics(0)
+    g.synchronize()
+    with_diag = time.perf_counter() - t0
+    return {"every": every, "diag_ms": round(ms, 4), "diag_alg_bytes": alg,
+            "diag_GBps": round(alg / (ms * 1e-3) / 1e9, 1), "diag_frac_of_8TBps": round(alg / (ms * 1e-3) / 1e9 /
+                                                                                         HBM_PEAK_GBS, 4),
+            "overhead_ms_per_step": round((with_diag - plain) / steps * 1e3, 4),
+            "plain_ms_per_step": round(plain / steps * 1e3, 4),
+            "last": {"kinetic_energy": d["kinetic_energy"], "mass": d["mass"],
+                     "force_on_solid": [float(v) for v in d["force_on_solid"]],
+                     "nonfinite_updates": d["nonfinite_updates"]}}
+
+
+def measure_format(storage, n, steps, warmup, diag_every=0):
     g, flags = cavity(n, storage)
     try:
         g.step(2)
         cfg = g.autotune(5)                      # leaves the state unchanged
         ms = time_steps(g, steps, warmup)
         d = g.diagnostics(0)
+        diag = diag_cost(g, flags, 19, storage, diag_every, 5 * diag_every) if diag_every else None
     finally:
         g.close()
     N = n ** 3
@@ -103,7 +148,8 @@ def measure_format(storage, n, steps, warmup):
             "mlups_fluid": n_fluid / (ms * 1e-3) / 1e6, "alg_bytes_per_launch": alg_bytes,
             "achieved_GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
             "kinetic_energy": d["kinetic_energy"], "nonfinite": d["nonfinite_cells"],
-            "launch": {k: cfg[k] for k in ("block", "cells_per_lane", "staged")}}
+            "nonfinite_updates": d["nonfinite_updates"],
+            "launch": {k: cfg[k] for k in ("block", "cells_per_lane")}, "diagnostics": diag}
 
 
 def periodic_box(steps=50, warmup=5):
@@ -139,7 +185,7 @@ def periodic_box(steps=50, warmup=5):
         rows.append({"velset": f"D{2 if q == 9 else 3}Q{q}", "collision": coll, "arith": arith, "storage": storage,
                      "cells": N, "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
                      "achieved_GBps": round(gbs, 1), "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
-                     "launch": {k: cfg[k] for k in ("mode", "block", "cells_per_lane", "staged")}})
+                     "launch": {k: cfg[k] for k in ("mode", "block", "cells_per_lane")}})
         print(f"[bench] periodic {rows[-1]['velset']} {coll} {arith}/{storage}: {rows[-1]['mlups']:.0f} MLUPs/s, "
               f"{gbs:.0f} GB/s", file=sys.stderr, flush=True)
     return rows
@@ -160,40 +206,44 @@ def ensemble(storage="fp16s", count=256, steps=50, warmup=10):
                               tau=sp["tau"], force=sp["force"]) for sp in specs]
     cells = sum(sp["nx"] * sp["ny"] * sp["nz"] for sp in specs)
     g = lbm.Lattices(params)
+    fluid = 0
     try:
         for k, sp in enumerate(specs):
             flags, rho, u = wl.ensemble_member_inputs(sp)
+            fluid += int(np.count_nonzero(flags == 0))
             g.set_boundaries(k, flags)
             g.set_rho_u(k, rho, u)
         out = {"lattices": count, "cells": cells, "storage": storage}
-        for name, cfg in [("per_lattice", dict(mode=0, block=128, cells_per_lane=1, staged=0, persistent=0,
+        for name, cfg in [("per_lattice", dict(mode=0, block=128, cells_per_lane=1, persistent=0,
                                                  graph_steps=0)),
-                          ("batched_rows", dict(mode=1, block=128, cells_per_lane=1, staged=0, persistent=0,
+                          ("batched_rows", dict(mode=1, block=128, cells_per_lane=1, persistent=0,
                                                 graph_steps=0)),
-                          ("batched", dict(mode=2, block=256, cells_per_lane=1, staged=0, persistent=0,
+                          ("batched", dict(mode=2, block=256, cells_per_lane=1, persistent=0,
                                            graph_steps=0)),
-                          ("persistent", dict(mode=2, block=256, cells_per_lane=1, staged=0, persistent=8,
+                          ("persistent", dict(mode=2, block=256, cells_per_lane=1, persistent=8,
                                               graph_steps=0)),
-                          ("persistent_graph100", dict(mode=2, block=256, cells_per_lane=1, staged=0,
+                          ("persistent_graph100", dict(mode=2, block=256, cells_per_lane=1,
                                                        persistent=8, graph_steps=100))]:
             g.set_launch(**cfg)
             n = 100 if cfg["graph_steps"] else steps
             ms = time_steps(g, n, warmup if not cfg["graph_steps"] else 100)
             out[name + "_mlups"] = round(cells / (ms * 1e-3) / 1e6, 1)
-            print(f"[bench] ensemble {name}: {out[name + '_mlups']:.0f} MLUPs/s", file=sys.stderr, flush=True)
+            print(f"[bench] ensemble {storage} {name}: {out[name + '_mlups']:.0f} MLUPs/s", file=sys.stderr,
+                  flush=True)
         g.set_launch(graph_steps=0)
         best = g.autotune(3)
         g.set_launch(graph_steps=100)
         ms = time_steps(g, 100, 100)
-        out["autotuned"] = {k: best[k] for k in ("mode", "block", "cells_per_lane", "staged", "persistent")}
+        out["autotuned"] = {k: best[k] for k in ("mode", "block", "cells_per_lane", "persistent")}
         out["autotuned_graph100_mlups"] = round(cells / (ms * 1e-3) / 1e6, 1)
-        print(f"[bench] ensemble autotuned {out['autotuned']}: {out['autotuned_graph100_mlups']:.0f} MLUPs/s",
-              file=sys.stderr, flush=True)
-        alg = 0
-        for sp in specs:
-            N = sp["nx"] * sp["ny"] * sp["nz"]
-            alg += N * (2 * 19 * ddf_bytes(storage) + 1)
-        out["autotuned_GBps_upper"] = round(alg / (ms * 1e-3) / 1e9, 1)
+        print(f"[bench] ensemble {storage} autotuned {out['autotuned']}: {out['autotuned_graph100_mlups']:.0f} "
+              "MLUPs/s", file=sys.stderr, flush=True)
+        # algorithmic bytes: 2 Q b + 1 per fluid cell, the flag byte per wall cell
+        alg = fluid * (2 * 19 * ddf_bytes(storage) + 1) + (cells - fluid)
+        out["fluid_cells"] = fluid
+        out["autotuned_alg_bytes_per_step"] = alg
+        out["autotuned_GBps"] = round(alg / (ms * 1e-3) / 1e9, 1)
+        out["autotuned_frac_of_8TBps"] = round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         return out
     finally:
         g.close()
@@ -225,6 +275,7 @@ def karman(storages=("fp16s", "fp16c", "fp32"), steps=50, warmup=10):
             cfg = g.autotune(5)
             ms = time_steps(g, steps, warmup)
             d = g.diagnostics(0)
+            diag = diag_cost(g, flags, 27, storage, 10, 200)
         finally:
             g.close()
         alg = n_fluid * (2 * 27 * ddf_bytes(storage) + 1) + (N - n_fluid)
@@ -233,8 +284,8 @@ def karman(storages=("fp16s", "fp16c", "fp32"), steps=50, warmup=10):
                      "mlups": round(N / (ms * 1e-3) / 1e6, 1), "achieved_GBps": round(gbs, 1),
                      "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
                      "force_on_cylinder": [float(v) for v in d["force_on_solid"]],
-                     "nonfinite": d["nonfinite_cells"],
-                     "launch": {k: cfg[k] for k in ("block", "cells_per_lane", "staged")}})
+                     "nonfinite": d["nonfinite_cells"], "drag_every_10": diag,
+                     "launch": {k: cfg[k] for k in ("block", "cells_per_lane")}})
         print(f"[bench] karman D3Q27 {storage}: {rows[-1]['mlups']:.0f} MLUPs/s, {gbs:.0f} GB/s",
               file=sys.stderr, flush=True)
     return {"workload": "Karman channel 1024x256x64, D3Q27 TRT, cylinder R 16, EQ inflow/outflow u 0.05, "
@@ -293,27 +344,35 @@ def traffic_from_profile(storage):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(budget_s=15.0):
+def cpu_baseline(budget_s=12.0):
     """The FP64 CPU reference timed on the host cores: the same cavity at a
-    reduced 96^3, D3Q19 TRT, FP64 arithmetic with FP16S storage emulation,
-    as many steps as fit the time budget (at least 2)."""
+    reduced 128^3, D3Q19 TRT, FP64 arithmetic with FP16S storage emulation,
+    as many steps as fit the time budget (at least 2) with all the threads
+    OpenMP is given, then the same on one thread."""
     import oracle
     import lbm_workloads as wl
-    n = 96
+    n = 128
     flags = wl.cavity_flags(n, n, n)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    lat = oracle.Lattice(n, n, n, q=19, tau=0.6, collision="trt", storage=HEADLINE,
-                         wall_u=(0.0, 0.1, 0.0), flags=flags, nthreads=threads).init()
-    t0 = time.perf_counter()
-    lat.step(1)
-    one = time.perf_counter() - t0
-    steps = max(2, int(budget_s / max(one, 1e-3)))
-    t0 = time.perf_counter()
-    lat.step(steps)
-    dt = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPs/s", "cores": threads, "kind": "oracle",
+
+    def rate(nthreads, budget):
+        lat = oracle.Lattice(n, n, n, q=19, tau=0.6, collision="trt", storage=HEADLINE,
+                             wall_u=(0.0, 0.1, 0.0), flags=flags, nthreads=nthreads).init()
+        t0 = time.perf_counter()
+        lat.step(1)
+        one = time.perf_counter() - t0
+        steps = max(2, int(budget / max(one, 1e-3)))
+        t0 = time.perf_counter()
+        lat.step(steps)
+        dt = time.perf_counter() - t0
+        return n ** 3 * steps / dt / 1e6, steps, dt
+
+    v, steps, dt = rate(threads, budget_s)
+    v1, steps1, dt1 = rate(1, budget_s / 2)
+    return {"value": v, "unit": "MLUPs/s", "cores": threads, "kind": "oracle",
             "sample": f"cavity {n}^3 D3Q19 TRT FP64 arithmetic, FP16S storage emulated, {steps} steps, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s on {threads} threads; {steps1} steps, {dt1:.1f} s on 1 thread",
+            "one_core_value": v1}
 
 
 def main():
@@ -325,7 +384,7 @@ def main():
     ap.add_argument("--formats", default="all", help="'all', 'headline' or a comma list")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-lattice ensemble")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-lattice ensembles")
     ap.add_argument("--no-karman", action="store_true", help="skip the full-size Karman channel (D3Q27)")
     ap.add_argument("--no-periodic", action="store_true",
                     help="skip the periodic-box runs (the paper's performance workload, other velocity sets)")
@@ -346,7 +405,7 @@ def main():
     results = {}
     for s in formats:
         print(f"[bench] {s} {args.n}^3 ...", file=sys.stderr, flush=True)
-        results[s] = measure_format(s, args.n, args.steps, args.warmup)
+        results[s] = measure_format(s, args.n, args.steps, args.warmup, diag_every=100 if s == HEADLINE else 0)
         print(f"[bench] {s}: {results[s]['mlups']:.0f} MLUPs/s, "
               f"{results[s]['achieved_GBps']:.0f} GB/s, launch {results[s]['launch']}",
               file=sys.stderr, flush=True)
@@ -360,7 +419,7 @@ def main():
     ens = None
     if not args.no_ensemble:
         print("[bench] ensemble of 256 lattices", file=sys.stderr, flush=True)
-        ens = ensemble()
+        ens = {s: ensemble(s) for s in ("fp16s", "fp16c")}
     kar = None
     if not args.no_karman:
         print("[bench] Karman channel 1024x256x64", file=sys.stderr, flush=True)

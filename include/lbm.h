@@ -59,7 +59,7 @@ typedef enum {
 
 /* Velocity sets (Sec. 2.1, Table 1), named by their number of directions:
  * rest first, then opposite pairs (2k-1, 2k).  D2Q9 needs nz = 1.  Several
- * cells per lane and the LDS-staged kernel exist for D3Q19 and D3Q27.  (D3Q7
+ * cells per lane exist for D3Q19 and D3Q27.  (D3Q7
  * and D3Q13 of Table 1 are not offered: with the equilibrium of Sec. 2.2
  * D3Q7 does not conserve momentum (its c_s^2 is 1/4) and D3Q13 lacks the
  * fourth-order isotropy of the viscous stress.) */
@@ -110,7 +110,11 @@ typedef struct {
 } lbm_params;
 
 /* FP64 diagnostics of one lattice, summed over fluid cells (neither SOLID
- * nor EQ) in a fixed order, so repeated calls give identical results. */
+ * nor EQ) in a fixed order, so repeated calls give identical results.  The
+ * sums are the discrete sums of the paper's diagnostics: the kinetic energy
+ * of the Taylor-Green runs (Sec. 4.2) and the velocity error norm of the
+ * Poiseuille runs (Sec. 4.1); mass and momentum are what the collision
+ * conserves (appendix "LBM equations in a nutshell"). */
 typedef struct {
     double mass;             /* sum of rho */
     double momentum[3];      /* sum of rho u */
@@ -118,8 +122,13 @@ typedef struct {
     double u_max;            /* max |u| */
     double l2_error;         /* sqrt(sum |u - u_ref|^2 / sum |u_ref|^2); -1 without u_ref */
     double force_on_solid[3];/* momentum exchange into SOLID cells, this time step */
-    int64_t nonfinite_cells; /* fluid cells with non-finite rho or u */
+    int64_t nonfinite_cells; /* fluid cells with non-finite rho or u (decoded state) */
     int64_t step;            /* time steps taken since the last initialisation */
+    int64_t nonfinite_updates; /* cell updates since the last initialisation whose
+                                  density or velocity before the velocity clamp was
+                                  not finite, counted by the step before encoding:
+                                  the only sign of a blow-up in FP16C and the
+                                  posits, which have no NaN or Inf and saturate */
 } lbm_diag;
 
 /* How lbm_step launches the stream-collide kernel. */
@@ -127,18 +136,14 @@ typedef struct {
  * one launch per step over a table of row tiles (block * cells_per_lane cells
  * of one row) of every lattice.  DENSE: one launch per step over tiles of
  * `block` consecutive cells in index order, which may span rows, so short
- * rows leave no lanes idle (one cell per lane, not staged). */
+ * rows leave no lanes idle (one cell per lane). */
 typedef enum { LBM_LAUNCH_PER_LATTICE = 0, LBM_LAUNCH_BATCHED = 1, LBM_LAUNCH_DENSE = 2 } lbm_launch_mode;
 typedef struct {
     int32_t mode;            /* lbm_launch_mode */
     int32_t block;           /* threads per workgroup: 64, 128, 256, 512 */
     int32_t cells_per_lane;  /* consecutive x cells per thread: 1, 2 (not FP64
                                 storage) or 4 (16-bit storage); every nx must
-                                be a multiple of it.  With staged = 1: cells
-                                per thread, 1 or 2 */
-    int32_t staged;          /* 1: LDS-staged kernel (row segments moved with
-                                16-byte accesses); every nx must be a multiple
-                                of 16 / bytes per DDF */
+                                be a multiple of it */
     int32_t persistent;      /* BATCHED/DENSE: workgroups per CU of a persistent
                                 grid walking the tile table; 0 = one workgroup
                                 per tile */
@@ -158,7 +163,9 @@ typedef struct {
 typedef void* (*lbm_alloc_fn)(size_t bytes, void* ctx);
 typedef void (*lbm_free_fn)(void* ptr, void* ctx);
 
-/* Create n_lattices >= 1 lattices described by params[0..n_lattices-1].
+/* Create n_lattices >= 1 lattices described by params[0..n_lattices-1]: the
+ * state of the paper's kernels (two DDF buffers for the one-step pull
+ * scheme, Sec. 5 and Table 3; a flag byte per cell).
  * All must share q, collision, storage and arith (else LBM_EUNSUPPORTED).
  * stream: a hipStream_t, or NULL for the null stream.  alloc/free_: optional
  * device allocator (both or neither); alloc_ctx is passed back to them.
@@ -193,8 +200,10 @@ lbm_status lbm_set_rho_u(lbm_handle* h, int32_t lattice, const double* rho, cons
  * the graph capture failed; steps already enqueued stay enqueued). */
 lbm_status lbm_step(lbm_handle* h, int64_t n_steps);
 
-/* Density and velocity of the current state (what the next step sees after
- * streaming; velocity includes half the body force, not clamped).  SOLID
+/* Density and velocity of the current state: the sums the paper's fields()
+ * takes (Sec. 2.2: density with the 1 of the shift added last, velocity by
+ * alternating pair sums), over what the next step sees after streaming;
+ * velocity includes half the body force, not clamped.  SOLID
  * cells report rho = 1 and the wall velocity, EQ cells their own moments.
  * rho: host double[N] or NULL; u: host double[3*N] or NULL.  Synchronises.
  * Errors: LBM_EINVAL (NULL handle, lattice out of range), LBM_ENOMEM
@@ -214,16 +223,21 @@ lbm_status lbm_get_rho_u(lbm_handle* h, int32_t lattice, double* rho, double* u)
 lbm_status lbm_set_ddf(lbm_handle* h, int32_t lattice, const void* host);
 lbm_status lbm_get_ddf(lbm_handle* h, int32_t lattice, void* host);
 
-/* FP64 diagnostics of one lattice.  u_ref: NULL or host double[3*N] for the
- * L2 error.  Fills *out; returns LBM_ENONFINITE (after filling) if
- * out->nonfinite_cells > 0.  Synchronises.  Other errors: LBM_EINVAL (NULL
- * handle or out, lattice out of range), LBM_ENOMEM (device copy of u_ref),
- * LBM_EDEVICE. */
+/* FP64 diagnostics of one lattice (see lbm_diag: the kinetic-energy sum of
+ * Sec. 4.2, the error norm of Sec. 4.1, conserved sums, momentum-exchange
+ * force).  u_ref: NULL or host double[3*N] for the L2 error.  Fills *out;
+ * returns LBM_ENONFINITE (after filling) if out->nonfinite_cells > 0 or
+ * out->nonfinite_updates > 0.  Synchronises.  Other errors: LBM_EINVAL
+ * (NULL handle or out, lattice out of range), LBM_ENOMEM (device copy of
+ * u_ref), LBM_EDEVICE. */
 lbm_status lbm_diagnostics(lbm_handle* h, int32_t lattice, const double* u_ref, lbm_diag* out);
 
 /* Launch configuration (see lbm_launch); invalid values are LBM_EINVAL and
  * leave the current configuration in place.  Setting one drops a captured
- * graph (it is captured again at the next lbm_step). */
+ * graph (it is captured again at the next lbm_step).  If the batched tile
+ * table cannot be built (LBM_ENOMEM, LBM_EDEVICE) the previous configuration
+ * is restored; should that fail too, lbm_step returns LBM_EINVAL for batched
+ * launches until a configuration is set successfully. */
 lbm_status lbm_set_launch(lbm_handle* h, const lbm_launch* cfg);
 lbm_status lbm_get_launch(lbm_handle* h, lbm_launch* cfg);
 

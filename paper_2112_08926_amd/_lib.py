@@ -49,19 +49,21 @@ class LbmDiag(ctypes.Structure):
     _fields_ = [("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
                 ("kinetic_energy", ctypes.c_double), ("u_max", ctypes.c_double),
                 ("l2_error", ctypes.c_double), ("force_on_solid", ctypes.c_double * 3),
-                ("nonfinite_cells", ctypes.c_int64), ("step", ctypes.c_int64)]
+                ("nonfinite_cells", ctypes.c_int64), ("step", ctypes.c_int64),
+                ("nonfinite_updates", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {"mass": self.mass, "momentum": np.array(self.momentum[:]),
                 "kinetic_energy": self.kinetic_energy, "u_max": self.u_max,
                 "l2_error": self.l2_error, "force_on_solid": np.array(self.force_on_solid[:]),
-                "nonfinite_cells": int(self.nonfinite_cells), "step": int(self.step)}
+                "nonfinite_cells": int(self.nonfinite_cells), "step": int(self.step),
+                "nonfinite_updates": int(self.nonfinite_updates)}
 
 
 class LbmLaunch(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("cells_per_lane", ctypes.c_int32), ("staged", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
+                ("cells_per_lane", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -160,15 +162,6 @@ def _host_ptr(a: np.ndarray | None):
     return None if a is None else a.ctypes.data_as(_P)
 
 
-def _sized(a, dtype, n: int, what: str) -> np.ndarray:
-    """C-ordered copy (or view) of `a` as `dtype`; the library reads exactly
-    n elements from it, so any other size is refused here."""
-    c = np.ascontiguousarray(a, dtype=dtype)
-    if c.size != n:
-        raise ValueError(f"{what}: {c.size} elements, the lattice needs {n}")
-    return c
-
-
 def make_params(nx, ny, nz, q=19, collision="srt", storage="fp32", arith="fp32", tau=0.6,
                 trt_magic=0.25, force=(0.0, 0.0, 0.0), wall_u=(0.0, 0.0, 0.0), eq_rho=1.0,
                 eq_u=(0.0, 0.0, 0.0), unshifted=False) -> LbmParams:
@@ -205,14 +198,23 @@ def lbm_create(params, stream=None, allocator: _TorchAllocator | None = None):
     return h
 
 
-def lbm_set_boundaries(h, lattice: int, flags: np.ndarray):
-    fl = np.ascontiguousarray(flags, dtype=np.uint8)
+def _check_host(a, n: int, dtype, what: str) -> np.ndarray:
+    """The library reads or writes exactly n elements of `dtype` at a host
+    pointer; refuse anything else instead of letting it run past the array."""
+    c = np.ascontiguousarray(a, dtype=dtype)
+    if c.size != n:
+        raise ValueError(f"{what}: {c.size} elements, the lattice needs {n}")
+    return c
+
+
+def lbm_set_boundaries(h, lattice: int, flags: np.ndarray, N: int):
+    fl = _check_host(flags, N, np.uint8, "flags")
     _check(library().lbm_set_boundaries(h, lattice, _host_ptr(fl)))
 
 
-def lbm_set_rho_u(h, lattice: int, rho: np.ndarray | None = None, u: np.ndarray | None = None):
-    r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
-    v = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+def lbm_set_rho_u(h, lattice: int, N: int, rho: np.ndarray | None = None, u: np.ndarray | None = None):
+    r = None if rho is None else _check_host(rho, N, np.float64, "rho")
+    v = None if u is None else _check_host(u, 3 * N, np.float64, "u")
     _check(library().lbm_set_rho_u(h, lattice, _host_ptr(r), _host_ptr(v)))
 
 
@@ -227,23 +229,39 @@ def lbm_get_rho_u(h, lattice: int, N: int):
     return rho, u
 
 
-def lbm_set_ddf(h, lattice: int, codes: np.ndarray):
-    c = np.ascontiguousarray(codes)
+def _ddf_dtype(bytes_per_ddf: int):
+    return {8: np.float64, 4: np.float32, 2: np.uint16}[bytes_per_ddf]
+
+
+def lbm_set_ddf(h, lattice: int, codes: np.ndarray, N: int, q: int):
+    """codes: q*N stored DDFs in the handle's storage type (float64, float32
+    or uint16 codes)."""
+    c = np.asarray(codes)
+    if c.size != q * N:
+        raise ValueError(f"codes: {c.size} elements, the lattice needs {q * N}")
+    dt = _ddf_dtype(lbm_info_get(h).bytes_per_ddf)
+    if c.dtype != dt:
+        raise ValueError(f"codes must be {np.dtype(dt).name} for this storage")
+    c = np.ascontiguousarray(c)
     _check(library().lbm_set_ddf(h, lattice, _host_ptr(c)))
 
 
-def lbm_get_ddf(h, lattice: int, out: np.ndarray):
-    if not out.flags.c_contiguous:
-        raise ValueError("out must be C-contiguous")
+def lbm_get_ddf(h, lattice: int, out: np.ndarray, N: int, q: int):
+    if not out.flags.c_contiguous or out.size != q * N:
+        raise ValueError(f"out must be a C-contiguous array of {q * N} elements")
+    dt = _ddf_dtype(lbm_info_get(h).bytes_per_ddf)
+    if out.dtype != dt:
+        raise ValueError(f"out must be {np.dtype(dt).name} for this storage")
     _check(library().lbm_get_ddf(h, lattice, _host_ptr(out)))
     return out
 
 
-def lbm_diagnostics(h, lattice: int, u_ref: np.ndarray | None = None) -> LbmDiag:
+def lbm_diagnostics(h, lattice: int, N: int, u_ref: np.ndarray | None = None) -> LbmDiag:
     """Returns the LbmDiag; raises LbmError on failure other than
-    LBM_ENONFINITE (then the returned record has nonfinite_cells > 0)."""
+    LBM_ENONFINITE (then the returned record has nonfinite_cells > 0 or
+    nonfinite_updates > 0)."""
     d = LbmDiag()
-    ref = None if u_ref is None else np.ascontiguousarray(u_ref, dtype=np.float64)
+    ref = None if u_ref is None else _check_host(u_ref, 3 * N, np.float64, "u_ref")
     rc = library().lbm_diagnostics(h, lattice, _host_ptr(ref), ctypes.byref(d))
     if rc not in (0, -5):
         _check(rc)
@@ -316,12 +334,10 @@ class Lattices:
         return _DTYPE.get(self.storage, np.uint16)
 
     def set_boundaries(self, k: int, flags):
-        lbm_set_boundaries(self.h, k, _sized(flags, np.uint8, self.N(k), "flags"))
+        lbm_set_boundaries(self.h, k, flags, self.N(k))
 
     def set_rho_u(self, k: int, rho=None, u=None):
-        n = self.N(k)
-        lbm_set_rho_u(self.h, k, None if rho is None else _sized(rho, np.float64, n, "rho"),
-                      None if u is None else _sized(u, np.float64, 3 * n, "u"))
+        lbm_set_rho_u(self.h, k, self.N(k), rho, u)
 
     def step(self, n: int = 1):
         lbm_step(self.h, n)
@@ -331,20 +347,18 @@ class Lattices:
 
     def get_ddf(self, k: int = 0) -> np.ndarray:
         out = np.empty((self.q, self.N(k)), dtype=self.ddf_dtype())
-        return lbm_get_ddf(self.h, k, out)
+        return lbm_get_ddf(self.h, k, out, self.N(k), self.q)
 
     def set_ddf(self, k: int, codes):
-        lbm_set_ddf(self.h, k, _sized(codes, self.ddf_dtype(), self.q * self.N(k), "codes"))
+        lbm_set_ddf(self.h, k, np.asarray(codes).astype(self.ddf_dtype(), copy=False), self.N(k), self.q)
 
     def diagnostics(self, k: int = 0, u_ref=None) -> dict:
-        ref = None if u_ref is None else _sized(u_ref, np.float64, 3 * self.N(k), "u_ref")
-        return lbm_diagnostics(self.h, k, ref).as_dict()
+        return lbm_diagnostics(self.h, k, self.N(k), u_ref).as_dict()
 
-    def set_launch(self, mode=None, block=None, cells_per_lane=None, staged=None, persistent=None,
-                   graph_steps=None):
+    def set_launch(self, mode=None, block=None, cells_per_lane=None, persistent=None, graph_steps=None):
         c = lbm_get_launch(self.h)
         for name, v in (("mode", mode), ("block", block), ("cells_per_lane", cells_per_lane),
-                        ("staged", staged), ("persistent", persistent), ("graph_steps", graph_steps)):
+                        ("persistent", persistent), ("graph_steps", graph_steps)):
             if v is not None:
                 setattr(c, name, int(v))
         lbm_set_launch(self.h, c)

@@ -34,6 +34,8 @@ struct LatDev {
     int32_t forced;          // any force component != 0
     float inv_nx, inv_ny;    // 1/nx, 1/ny rounded to float (cell-contiguous tiles)
     int32_t pad;
+    unsigned long long* nonfinite; // cell updates with a non-finite density or velocity
+                                   // before the clamp, since the last initialisation
 };
 
 // One workgroup's share of a batched step: cells x0 .. x0+T-1 of row (y, z)
@@ -52,7 +54,6 @@ struct EncEntry {
 struct StepLaunch {
     int q, storage, arith, collision;
     int block, cpl;
-    int staged;              // LDS-staged kernel (cpl = cells per thread)
     int dense;               // batched over cell-contiguous tiles of `block` cells
     int parity;
     const LatDev* lats;      // batched: device array of descriptors
@@ -72,7 +73,6 @@ hipError_t launch_moments(int q, int storage, int arith, const LatDev& lat, int 
                           double* rho, double* u, hipStream_t st);
 hipError_t launch_eq_codes(int q, int storage, int arith, const LatDev& lat, void* out,
                            const EncEntry* enc, hipStream_t st);
-size_t staged_lds_bytes(int q, int storage, int block, int cpl);
 
 // Per-format launch hooks, defined in kern_<format>.hip.
 #define LBM_DECLARE_FORMAT(NAME)                                                              \
@@ -85,7 +85,8 @@ size_t staged_lds_bytes(int q, int storage, int block, int cpl);
     hipError_t eq_codes_##NAME(int q, int arith, const LatDev& lat, void* out,               \
                                const EncEntry* enc, hipStream_t st);                         \
     hipError_t diag_##NAME(int q, int arith, const LatDev& lat, int parity,                  \
-                           const double* u_ref, double* partials, int nblocks, hipStream_t st);
+                           const double* u_ref, double* partials, int nblocks, uint32_t segs,   \
+                           hipStream_t st);
 LBM_DECLARE_FORMAT(fp64)
 LBM_DECLARE_FORMAT(fp32)
 LBM_DECLARE_FORMAT(fp16)
@@ -96,7 +97,8 @@ LBM_DECLARE_FORMAT(p16_1s)
 LBM_DECLARE_FORMAT(p16_2c)
 #undef LBM_DECLARE_FORMAT
 
-constexpr int kDiagBlocks = 1024;   // workgroups of the first diagnostics pass
-constexpr int kDiagFields = 12;     // mass, mom x3, ke, err2, ref2, force x3, nonfinite, umax
+constexpr int kDiagBlocks = 2048;   // most workgroups of the first diagnostics pass (8 per CU)
+constexpr int kDiagThreads = 256;   // threads per workgroup of the first pass = cells per row tile
+constexpr int kDiagFields = 12;     // mass, mom x3, ke, err2, ref2, force x3, nonfinite, max |u|^2
 
 }  // namespace lbm

@@ -92,9 +92,14 @@ template <> struct VelSet<15> {
 
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
+// The listing's velocity limit, OpenCL's clamp(v, -c, c) with c = 1/sqrt(3),
+// which that language defines as fmin(fmax(v, -c), c).  fmax and fmin return
+// the other operand when one is NaN, so a NaN component becomes -c (a cell of
+// zero density would otherwise turn its whole equilibrium into NaN).
 template <class A> __device__ __forceinline__ A clamp_c(A v) {
     const A cs = (A)0.57735026918962576451;   // lattice speed of sound 1/sqrt(3)
-    return v < -cs ? -cs : (v > cs ? cs : v);
+    if constexpr (sizeof(A) == 4) return __builtin_fminf(__builtin_fmaxf(v, -cs), cs);
+    else return __builtin_fmin(__builtin_fmax(v, -cs), cs);
 }
 
 // c . v for a lattice direction with components in {-1, 0, 1}, written with
@@ -469,8 +474,10 @@ __device__ __forceinline__ void collide_mrt(A w, A rho, A rhom1, A C, A u3x, A u
 // where the division's rounding is visible); otherwise j * (1/rho) with the
 // hardware reciprocal, whose error (~1e-7 relative) is far below a 16-bit
 // storage step.
+// bad: the density or a velocity component before the clamp is not finite
+// (a blow-up that the clamp and the saturating 16-bit encoders would hide).
 template <int Q, int COLL, class A, bool EXACT_DIV, int E>
-__device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo)[Q]) {
+__device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo)[Q], bool& bad) {
     static_assert(!EXACT_DIV || E == 0, "scaled units only with the reciprocal path");
     constexpr double kSc = (double)(1u << E);
     const A sc = (A)kSc;
@@ -488,19 +495,21 @@ __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo
         j[1] += (A)(0.5 * kSc) * Fy;
         j[2] += (A)(0.5 * kSc) * Fz;
     }
-    A ux, uy, uz;
+    A vx, vy, vz;                                            // velocity before the clamp
     if constexpr (EXACT_DIV) {
-        ux = clamp_c(j[0] / rho);
-        uy = clamp_c(j[1] / rho);
-        uz = clamp_c(j[2] / rho);
+        vx = j[0] / rho;
+        vy = j[1] / rho;
+        vz = j[2] / rho;
     } else {
         A inv;
         if constexpr (sizeof(A) == 4) inv = (A)(1.0 / kSc) * __builtin_amdgcn_rcpf(rho);
         else inv = (A)(1.0 / kSc) / rho;
-        ux = clamp_c(j[0] * inv);
-        uy = clamp_c(j[1] * inv);
-        uz = clamp_c(j[2] * inv);
+        vx = j[0] * inv;
+        vy = j[1] * inv;
+        vz = j[2] * inv;
     }
+    bad = !(__builtin_isfinite(rho) && __builtin_isfinite(vx) && __builtin_isfinite(vy) && __builtin_isfinite(vz));
+    const A ux = clamp_c(vx), uy = clamp_c(vy), uz = clamp_c(vz);
     const A C = (A)(-3) * fmaa(ux, ux, fmaa(uy, uy, uz * uz));
     const A rhom1 = rho - shift;                             // rho - 1 (shifted) or rho
     const A u3x = (A)3 * ux, u3y = (A)3 * uy, u3z = (A)3 * uz;
@@ -607,6 +616,16 @@ __device__ __forceinline__ typename Codec<F>::T out_code(uint32_t fl, typename C
     return code;
 }
 
+// Adds the wavefront's cells whose update had a non-finite density or
+// velocity (`bad`) to the lattice's counter: one ballot, and, only in a
+// wavefront that holds such a cell, one vector atomic by a single lane.
+__device__ __forceinline__ void count_nonfinite(const LatDev& L, bool bad) {
+    const uint64_t b = __ballot(bad);
+    if (b != 0 && (int)__lane_id() == __builtin_ctzll(b))
+        __hip_atomic_fetch_add((LBM_GLOBAL unsigned long long*)L.nonfinite, (unsigned long long)__popcll(b),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------ one tile of the step
 template <int Q, int F, class A, int COLL>
 __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z,
@@ -629,7 +648,9 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     A f[Q], fo[Q];
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
     pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
-    if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
+    bool bad = false;
+    if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
+    count_nonfinite(L, bad);
     T eq[Q];
     eq_codes_if<Q, F>(L, __any((fl & F_EQ) != 0), eq);
     const size_t plane = L.plane;
@@ -679,7 +700,9 @@ __device__ __forceinline__ void step_tile_dense(const LatDev& L, uint32_t x0, ui
     A f[Q], fo[Q];
     pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);   // loads with the flag's
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
-    if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
+    bool bad = false;
+    if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
+    count_nonfinite(L, bad);
     T eq[Q];
     eq_codes_if<Q, F>(L, __any((fl & F_EQ) != 0), eq);
     const size_t plane = L.plane;
@@ -927,7 +950,9 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
                 }
             }
         }
-        collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
+        bool bad;
+        collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
+        count_nonfinite(L, bad && !special[k]);
 #pragma unroll
         for (int i = 0; i < Q; i++) vset<T, CPL>(out[i], k, Codec<F>::template store_raw<A>(fo[i], tab));
     }
@@ -958,154 +983,6 @@ __device__ __forceinline__ const EncEntry* stage_table(const EncEntry* g, EncEnt
         return s;
     } else {
         return nullptr;
-    }
-}
-
-// One lattice: workgroup b handles segment b % segs of row b / segs.
-// ------------------------------------------------------------ LDS-staged step
-// A workgroup of B threads owns a row segment of S = B*K cells.  Its waves
-// load, for every direction i, the segment of the source row (y - c_iy,
-// z - c_iz) with 16-byte accesses into LDS, plus the one element the x-shift
-// needs beyond the segment (periodic wrap), and the segment's flag bytes.
-// Each thread then pulls the DDFs of its K cells from LDS (the x-shift is an
-// LDS offset), collides, and -- after a barrier -- writes the new codes back
-// in place; the waves finally store every direction's segment of the own row
-// with 16-byte accesses.  Wall cells are written as zero and EQ cells with
-// the lattice's equilibrium codes, which is what both buffers hold there.
-// Requires nx to be a multiple of the elements per 16 bytes.
-template <class T> constexpr int kVecElems = 16 / (int)sizeof(T);
-
-template <int Q, class T>
-__host__ __device__ constexpr size_t staged_lds(int block, int cpl) {
-    return (size_t)Q * ((size_t)block * cpl + 2 * kVecElems<T>) * sizeof(T) + (size_t)block * cpl;
-}
-
-template <int Q, int F, class A, int COLL, int K>
-__device__ __forceinline__ void staged_tile(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z, int parity,
-                                            const EncEntry* tab, char* lds) {
-    using T = typename Codec<F>::T;
-    constexpr int VE = kVecElems<T>;
-    constexpr int OFF = VE;
-    const uint32_t B = blockDim.x;
-    const uint32_t S = B * K;
-    const uint32_t RS = S + 2 * OFF;                       // LDS row stride (elements)
-    T* s_ddf = (T*)lds;
-    uint8_t* s_fl = (uint8_t*)(s_ddf + (size_t)Q * RS);
-    const uint32_t nx = L.nx, ny = L.ny, nz = L.nz;
-    const uint32_t seg = min(S, nx - x0);                  // multiple of VE
-    const uint32_t nvec = seg / VE;
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = B >> 6;
-    const T* __restrict__ src = (const T*)L.f[parity];
-    T* __restrict__ dst = (T*)L.f[parity ^ 1];
-    const size_t plane = L.plane;
-    const uint32_t row = (y + z * ny) * nx;
-
-    // ---- load the source row segments
-    for (uint32_t i = wave; i < (uint32_t)Q; i += nwaves) {
-        const int cx = VelSet<Q>::c[i][0], cy = VelSet<Q>::c[i][1], cz = VelSet<Q>::c[i][2];
-        const uint32_t sy = wrap_add(y, -cy, ny), sz = wrap_add(z, -cz, nz);
-        const T* rp = src + (size_t)i * plane + (sy + sz * ny) * nx + x0;
-        T* lp = s_ddf + i * RS + OFF;
-        for (uint32_t k = lane; k < nvec; k += 64)
-            *(u32x4*)(lp + k * VE) = *(const LBM_GLOBAL u32x4*)(rp + k * VE);
-        if (lane == 0 && cx != 0) {
-            const T* r0 = rp - x0;
-            if (cx > 0) lp[-1] = ld_off(r0, x0 == 0 ? nx - 1 : x0 - 1);
-            else lp[seg] = ld_off(r0, x0 + seg == nx ? 0 : x0 + seg);
-        }
-    }
-    for (uint32_t k = threadIdx.x; k < seg / 2; k += B)
-        ((uint16_t*)s_fl)[k] = ((const LBM_GLOBAL uint16_t*)(L.flags + row + x0))[k];
-    __syncthreads();
-
-    // ---- collide the K cells of this thread
-    T codes[K][Q];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const uint32_t xl = threadIdx.x + k * B;
-        if (xl >= seg) continue;
-        const uint8_t fl = s_fl[xl];
-        if (fl & F_SOLID) {
-#pragma unroll
-            for (int i = 0; i < Q; i++) codes[k][i] = Codec<F>::template store<A>((A)0, tab);
-        } else if (fl & F_EQ) {
-#pragma unroll
-            for (int i = 0; i < Q; i++) codes[k][i] = eq_code<F>(L, i);
-        } else {
-            A f[Q], fo[Q];
-#pragma unroll
-            for (int i = 0; i < Q; i++)
-                f[i] = load_ddf<Q, F, A, true>(s_ddf[i * RS + OFF + xl - VelSet<Q>::c[i][0]]);
-            const bool near = (fl & F_NEAR) != 0;
-            if (__any(near)) {
-                const uint32_t x = x0 + xl;
-                const uint32_t xm = x == 0 ? nx - 1 : x - 1;
-                const uint32_t xp = x + 1 == nx ? 0 : x + 1;
-                const uint32_t m = near ? ld_mask(L.wall_mask, row + x) : 0u;
-                RowCtx rc;
-                make_rows(L, y, z, rc);
-#pragma unroll
-                for (int i = 1; i < Q; i++) {
-                    if (m & (1u << i)) {
-                        A v = load_ddf<Q, F, A, true>(ld_off(src + (size_t)opp(i) * plane, row + x));
-                        if (m & 0x80000000u) {
-                            const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
-                            if (fs & F_MOVING) {
-                                const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
-                                                 VelSet<Q>::c[i][2] * L.wall_u[2]);
-                                v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, true>()) * cu;
-                            }
-                        }
-                        f[i] = v;
-                    }
-                }
-            }
-            collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo);
-#pragma unroll
-            for (int i = 0; i < Q; i++) codes[k][i] = Codec<F>::template store_raw<A>(fo[i], tab);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const uint32_t xl = threadIdx.x + k * B;
-        if (xl < seg) {
-#pragma unroll
-            for (int i = 0; i < Q; i++) s_ddf[i * RS + OFF + xl] = codes[k][i];
-        }
-    }
-    __syncthreads();
-
-    // ---- store the own row segment of every direction
-    for (uint32_t i = wave; i < (uint32_t)Q; i += nwaves) {
-        T* rp = dst + (size_t)i * plane + row + x0;
-        const T* lp = s_ddf + i * RS + OFF;
-        for (uint32_t k = lane; k < nvec; k += 64)
-            *(LBM_GLOBAL u32x4*)(rp + k * VE) = *(const u32x4*)(lp + k * VE);
-    }
-    __syncthreads();                                        // LDS is reused by the next tile
-}
-
-template <int Q, int F, class A, int COLL, int K>
-__global__ void __launch_bounds__(512) k_step_staged_single(LatDev L, int parity, uint32_t segs,
-                                                            const EncEntry* __restrict__ enc) {
-    extern __shared__ __align__(16) char lds_dyn[];
-    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
-    const EncEntry* tab = stage_table<F>(enc, s_tab);
-    // grid (ny, segments, nz), as for the unstaged kernel
-    staged_tile<Q, F, A, COLL, K>(L, blockIdx.y * blockDim.x * K, blockIdx.x, blockIdx.z, parity, tab, lds_dyn);
-}
-
-template <int Q, int F, class A, int COLL, int K>
-__global__ void __launch_bounds__(512) k_step_staged_batched(const LatDev* __restrict__ lats,
-                                                             const Tile* __restrict__ tiles, uint32_t ntiles,
-                                                             int parity, const EncEntry* __restrict__ enc) {
-    extern __shared__ __align__(16) char lds_dyn[];
-    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
-    const EncEntry* tab = stage_table<F>(enc, s_tab);
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const Tile tl = tiles[t];
-        staged_tile<Q, F, A, COLL, K>(lats[tl.lat], tl.x0, tl.y, tl.z, parity, tab, lds_dyn);
     }
 }
 
@@ -1293,22 +1170,50 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], d
     }
 }
 
-// First pass: a fixed grid of kDiagBlocks workgroups, each a fixed strided
-// subset of the cells, so the result does not depend on timing.
+// First pass.  The lattice is cut into row tiles of kDiagThreads cells (segs
+// per row, the step's decomposition: one scalar division per tile for the
+// row's y and z, neighbour rows and wrap workgroup-uniform, the wall mask
+// read only by wavefronts next to a wall).  Workgroup b takes the tiles
+// b, b + G, b + 2G, ... of a fixed grid of G workgroups, so every lane sums
+// its cells in a fixed order and the result does not depend on timing.
+// Accumulators per lane, in FP64: mass, momentum (3), kinetic energy, error
+// and reference norms, the momentum exchange into walls (3), non-finite
+// cells, and the largest |u|^2 (its square root is taken once, at the end).
+// The moments are those the next step sees after streaming (velocity with
+// F/2, not clamped), in the arithmetic precision of the step.
 template <int Q, int F, class A>
-__global__ void __launch_bounds__(256) k_diag(LatDev L, int parity, const double* __restrict__ u_ref,
-                                              double* __restrict__ partials) {
+__global__ void __launch_bounds__(kDiagThreads) k_diag(LatDev L, int parity, const double* __restrict__ u_ref,
+                                                       double* __restrict__ partials, uint32_t segs) {
     using T = typename Codec<F>::T;
-    const size_t N = (size_t)L.nx * L.ny * L.nz;
+    const uint32_t N = L.nx * L.ny * L.nz;                   // < 2^31
+    const uint32_t ntiles = L.ny * L.nz * segs;              // <= N + ny nz < 2^32
     double acc[kDiagFields];
+#pragma unroll
     for (int k = 0; k < kDiagFields; k++) acc[k] = 0.0;
     const T* __restrict__ src = (const T*)L.f[parity];
-    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
-        uint32_t fl;
-        A rho, u[3], f[Q];
-        cell_moments<Q, F, A>(L, parity, (uint32_t)n, fl, rho, u, f);
+    const size_t plane = L.plane;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint32_t row = t / segs;                       // workgroup-uniform
+        const uint32_t x = (t - row * segs) * kDiagThreads + threadIdx.x;
+        if (x >= L.nx) continue;
+        const uint32_t y = row % L.ny, z = row / L.ny;
+        RowCtx rc;
+        make_rows(L, y, z, rc);
+        const uint32_t n = rc.rows[4] + x;
+        const uint8_t fl = ld_off(L.flags, n);
+        const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
+        const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+        A f[Q];
+        pull<Q, F, A, false>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
         if (fl & (F_SOLID | F_EQ)) continue;
-        const double r = (double)rho, ux = (double)u[0], uy = (double)u[1], uz = (double)u[2];
+        A rho, j[3];
+        fields<Q, A>(f, (A)L.shift, rho, j);
+        if (L.forced) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) j[a] += (A)0.5 * (A)L.force[a];
+        }
+        const double r = (double)rho, ux = (double)(j[0] / rho), uy = (double)(j[1] / rho),
+                     uz = (double)(j[2] / rho);
         if (!(isfinite(r) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
             acc[10] += 1.0;
             continue;
@@ -1319,31 +1224,31 @@ __global__ void __launch_bounds__(256) k_diag(LatDev L, int parity, const double
         acc[3] += r * uz;
         const double u2 = ux * ux + uy * uy + uz * uz;
         acc[4] += 0.5 * r * u2;
-        acc[11] = fmax(acc[11], sqrt(u2));
+        acc[11] = fmax(acc[11], u2);
         if (u_ref) {
-            const double rx = u_ref[n], ry = u_ref[N + n], rz = u_ref[2 * N + n];
+            const double rx = u_ref[n], ry = u_ref[(size_t)N + n], rz = u_ref[2 * (size_t)N + n];
             acc[5] += (ux - rx) * (ux - rx) + (uy - ry) * (uy - ry) + (uz - rz) * (uz - rz);
             acc[6] += rx * rx + ry * ry + rz * rz;
         }
         if (fl & F_NEAR) {
-            // momentum exchange: every link to a wall source carries
-            // c_opp (2 (f*_opp + w_opp) + 6 w_i c_i.u_w) into the wall
-            const uint32_t x = n % L.nx, yz = n / L.nx, y = yz % L.ny, z = yz / L.ny;
-            RowCtx rc;
-            make_rows(L, y, z, rc);
-            const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
-            const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
-#pragma unroll
+            // momentum exchange: every link to a wall source x - c_i carries
+            // c_opp (2 (f*_opp + w_opp) + 6 w_i c_i.u_w) into the wall, f*_opp
+            // being what this cell sent towards the wall in the last step
+            const uint32_t m = ld_mask(L.wall_mask, n);
+#pragma unroll 1
             for (int i = 1; i < Q; i++) {
-                const uint8_t fs = L.flags[src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)];
-                if (!(fs & F_SOLID)) continue;
+                if (!((m >> i) & 1u)) continue;
                 const int o = opp(i);
-                const double fo = (double)Codec<F>::template load<A>(src[(size_t)o * L.plane + n]) +
+                const double fo = (double)load_ddf<Q, F, A, false>(ld_off(src + (size_t)o * plane, n)) +
                                   VelSet<Q>::w(o) * L.shift;
                 double mv = 0.0;
-                if (fs & F_MOVING)
-                    mv = 6.0 * VelSet<Q>::w(i) * (VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
-                                                  VelSet<Q>::c[i][2] * L.wall_u[2]);
+                if (m & 0x80000000u) {
+                    const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
+                    if (fs & F_MOVING)
+                        mv = 6.0 * VelSet<Q>::w(i) *
+                             (VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                              VelSet<Q>::c[i][2] * L.wall_u[2]);
+                }
                 acc[7] += VelSet<Q>::c[o][0] * (2.0 * fo + mv);
                 acc[8] += VelSet<Q>::c[o][1] * (2.0 * fo + mv);
                 acc[9] += VelSet<Q>::c[o][2] * (2.0 * fo + mv);
@@ -1381,37 +1286,14 @@ struct FormatLaunchers {
                            s.ntiles, s.parity, s.enc);
         return hipGetLastError();
     }
-    template <int Q, class A, int COLL, int K>
-    static hipError_t staged_single_k(const StepLaunch& s, const LatDev& L) {
-        using T = typename Codec<F>::T;
-        const uint32_t per_wg = (uint32_t)s.block * K;
-        const uint32_t segs = (L.nx + per_wg - 1) / per_wg;
-        const size_t lds = staged_lds<Q, T>(s.block, K);
-        hipLaunchKernelGGL((k_step_staged_single<Q, F, A, COLL, K>), dim3(L.ny, segs, L.nz), dim3(s.block), lds,
-                           s.stream, L, s.parity, segs, s.enc);
-        return hipGetLastError();
-    }
-    template <int Q, class A, int COLL, int K>
-    static hipError_t staged_batched_k(const StepLaunch& s) {
-        using T = typename Codec<F>::T;
-        const size_t lds = staged_lds<Q, T>(s.block, K);
-        hipLaunchKernelGGL((k_step_staged_batched<Q, F, A, COLL, K>), dim3(s.grid), dim3(s.block), lds, s.stream,
-                           s.lats, s.tiles, s.ntiles, s.parity, s.enc);
-        return hipGetLastError();
-    }
-    // several cells per lane and the LDS-staged kernel are built for D3Q19
-    // and D3Q27 with SRT and TRT; the other sets and MRT run one cell per lane
+    // several cells per lane are built for D3Q19 and D3Q27 with SRT and
+    // TRT; the other sets and MRT run one cell per lane
     static constexpr bool kWide(int Q) { return Q == 19 || Q == 27; }
 
     template <int Q, class A, int COLL>
     static hipError_t single_qac(const StepLaunch& s, const LatDev& L) {
-        if (s.cpl == 1 && !s.staged) return single_cpl<Q, A, COLL, 1>(s, L);
+        if (s.cpl == 1) return single_cpl<Q, A, COLL, 1>(s, L);
         if constexpr (kWide(Q) && COLL != 2) {
-            if (s.staged) {
-                if (s.cpl == 1) return staged_single_k<Q, A, COLL, 1>(s, L);
-                if (s.cpl == 2) return staged_single_k<Q, A, COLL, 2>(s, L);
-                return hipErrorInvalidValue;
-            }
             if constexpr (kMaxCpl >= 2)
                 if (s.cpl == 2) return single_cpl<Q, A, COLL, 2>(s, L);
             if constexpr (kMaxCpl >= 4)
@@ -1421,14 +1303,9 @@ struct FormatLaunchers {
     }
     template <int Q, class A, int COLL>
     static hipError_t batched_qac(const StepLaunch& s) {
-        if (s.dense) return (s.cpl == 1 && !s.staged) ? dense_k<Q, A, COLL>(s) : hipErrorInvalidValue;
-        if (s.cpl == 1 && !s.staged) return batched_cpl<Q, A, COLL, 1>(s);
+        if (s.dense) return s.cpl == 1 ? dense_k<Q, A, COLL>(s) : hipErrorInvalidValue;
+        if (s.cpl == 1) return batched_cpl<Q, A, COLL, 1>(s);
         if constexpr (kWide(Q) && COLL != 2) {
-            if (s.staged) {
-                if (s.cpl == 1) return staged_batched_k<Q, A, COLL, 1>(s);
-                if (s.cpl == 2) return staged_batched_k<Q, A, COLL, 2>(s);
-                return hipErrorInvalidValue;
-            }
             if constexpr (kMaxCpl >= 2)
                 if (s.cpl == 2) return batched_cpl<Q, A, COLL, 2>(s);
             if constexpr (kMaxCpl >= 4)

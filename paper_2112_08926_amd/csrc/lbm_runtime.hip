@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "lbm.h"
@@ -124,26 +125,36 @@ hipError_t launch_eq_codes(int q, int storage, int arith, const LatDev& lat, voi
     LBM_FORMAT_SWITCH(storage, E)
 #undef E
 }
-size_t staged_lds_bytes(int q, int storage, int block, int cpl) {
-    const int b = storage == S_FP64 ? 8 : (storage == S_FP32 ? 4 : 2);
-    const size_t ve = 16 / b;
-    return (size_t)q * ((size_t)block * cpl + 2 * ve) * b + (size_t)block * cpl;
-}
 }  // namespace lbm
 
 // ------------------------------------------------------------------ small kernels
+// Second pass of the diagnostics: one workgroup of 256 threads sums the
+// first pass's per-workgroup partials (the last field by max) in a fixed
+// order -- thread t the partials t, t + 256, ..., then a fixed tree -- so
+// repeated calls give identical results.
 __global__ void __launch_bounds__(256) k_diag_finish(const double* __restrict__ partials, int nblocks,
                                                      double* __restrict__ out) {
-    // one workgroup; thread t owns field t and sums the partials in block order
+    __shared__ double s[kDiagFields][256];
     const int t = threadIdx.x;
-    if (t < kDiagFields) {
-        double v = t == kDiagFields - 1 ? 0.0 : 0.0;
-        for (int b = 0; b < nblocks; b++) {
-            const double p = partials[(size_t)b * kDiagFields + t];
-            v = (t == kDiagFields - 1) ? fmax(v, p) : v + p;
+#pragma unroll
+    for (int k = 0; k < kDiagFields; k++) {
+        double v = 0.0;
+        for (int b = t; b < nblocks; b += 256) {
+            const double p = partials[(size_t)b * kDiagFields + k];
+            v = (k == kDiagFields - 1) ? fmax(v, p) : v + p;
         }
-        out[t] = v;
+        s[k][t] = v;
     }
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int k = 0; k < kDiagFields; k++)
+                s[k][t] = (k == kDiagFields - 1) ? fmax(s[k][t], s[k][t + w]) : s[k][t] + s[k][t + w];
+        }
+        __syncthreads();
+    }
+    if (t < kDiagFields) out[t] = s[t][0];
 }
 
 __global__ void __launch_bounds__(256) k_encode(int storage, const float* __restrict__ in,
@@ -296,18 +307,34 @@ struct lbm_handle {
     // diagnostics scratch
     double* d_partials = nullptr;
     double* d_out = nullptr;
+    // per lattice: cell updates with a non-finite density or velocity before
+    // the clamp since the lattice was last initialised
+    unsigned long long* d_nonfinite = nullptr;
+    // size of every device allocation the handle holds (for device_bytes)
+    std::unordered_map<void*, size_t> sizes;
 };
 
+// Device memory of a handle, through the caller's allocator hooks if given.
+// Every allocation the library makes for a handle goes through here, also
+// short-lived staging buffers, so that a caller's allocator sees all of it.
 static void* dev_alloc(lbm_handle* h, size_t bytes) {
     void* p = nullptr;
     if (bytes == 0) bytes = 256;
     if (h->alloc) p = h->alloc(bytes, h->ctx);
     else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
-    if (p) h->device_bytes += (int64_t)bytes;
+    if (p) {
+        h->device_bytes += (int64_t)bytes;
+        h->sizes[p] = bytes;
+    }
     return p;
 }
 static void dev_free(lbm_handle* h, void* p) {
     if (!p) return;
+    auto it = h->sizes.find(p);
+    if (it != h->sizes.end()) {
+        h->device_bytes -= (int64_t)it->second;
+        h->sizes.erase(it);
+    }
     if (h->free_) h->free_(p, h->ctx);
     else (void)hipFree(p);
 }
@@ -425,11 +452,17 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
         return fail(LBM_EDEVICE, "no HIP device");
     }
     h->num_cus = prop.multiProcessorCount;
-    h->launch = {n_lattices > 1 ? LBM_LAUNCH_BATCHED : LBM_LAUNCH_PER_LATTICE, 256, 1, 0, 0, 0};
+    h->launch = {n_lattices > 1 ? LBM_LAUNCH_BATCHED : LBM_LAUNCH_PER_LATTICE, 256, 1, 0, 0};
     lbm_status st = device_table(h->storage, &h->enc);
     if (st != LBM_OK) { delete h; return st; }
     const int b = ddf_bytes(h->storage);
     h->lats.resize(n_lattices);
+    h->d_nonfinite = (unsigned long long*)dev_alloc(h, sizeof(unsigned long long) * n_lattices);
+    if (!h->d_nonfinite || hipMemsetAsync(h->d_nonfinite, 0, sizeof(unsigned long long) * n_lattices,
+                                          h->stream) != hipSuccess) {
+        lbm_destroy(h);
+        return fail(LBM_ENOMEM, "device allocation of the non-finite counters failed");
+    }
     for (int k = 0; k < n_lattices; k++) {
         Lattice& L = h->lats[k];
         L.p = params[k];
@@ -456,6 +489,7 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
             return fail(LBM_EDEVICE, "hipMemsetAsync failed");
         }
         fill_dev(L, h->arith);
+        L.dev.nonfinite = h->d_nonfinite + k;
         if (launch_eq_codes(h->q, h->storage, h->arith, L.dev, L.eq_codes, h->enc, h->stream) != hipSuccess) {
             lbm_destroy(h);
             return fail(LBM_EDEVICE, "equilibrium code table failed");
@@ -500,7 +534,13 @@ extern "C" void lbm_destroy(lbm_handle* h) {
     dev_free(h, h->d_out);
     dev_free(h, h->d_lats);
     dev_free(h, h->d_tiles);
+    dev_free(h, h->d_nonfinite);
     delete h;
+}
+
+// Clears a lattice's count of non-finite updates (when it is initialised).
+static hipError_t reset_nonfinite(lbm_handle* h, int32_t k) {
+    return hipMemsetAsync(h->d_nonfinite + k, 0, sizeof(unsigned long long), h->stream);
 }
 
 static lbm_status check_lattice(lbm_handle* h, int32_t k) {
@@ -511,7 +551,11 @@ static lbm_status check_lattice(lbm_handle* h, int32_t k) {
 
 // ------------------------------------------------------------------ tiles
 // Tile table of the batched launch for the current block size: row segments
-// of `block` cells, lattice by lattice, row by row.
+// of `block` cells, lattice by lattice, row by row.  The old table is
+// withdrawn before anything can fail (with any graph that was captured with
+// it), and the new one is published only once it is on the device, so after
+// a failure the handle holds no table and lbm_step refuses batched launches
+// instead of reading a freed or short table.
 static lbm_status rebuild_tiles(lbm_handle* h) {
     const int T = h->launch.block * h->launch.cells_per_lane;
     const bool dense = h->launch.mode == LBM_LAUNCH_DENSE;
@@ -538,12 +582,22 @@ static lbm_status rebuild_tiles(lbm_handle* h) {
                         tiles.push_back(Tile{(uint16_t)k, (uint16_t)x0, (uint16_t)y, (uint16_t)z});
                 }
     }
+    drop_graph(h);
+    Tile* old = h->d_tiles;
+    h->d_tiles = nullptr;
+    h->ntiles = 0;
+    h->tiles_block = 0;
+    dev_free(h, old);
     if (tiles.size() >= 0xFFFFFFFFull) return fail(LBM_EINVAL, "too many tiles");
-    dev_free(h, h->d_tiles);
-    h->d_tiles = (Tile*)dev_alloc(h, sizeof(Tile) * std::max<size_t>(tiles.size(), 1));   // may be empty
-    if (!h->d_tiles) return fail(LBM_ENOMEM, "tile table allocation failed");
-    HIP_TRY(hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    Tile* t = (Tile*)dev_alloc(h, sizeof(Tile) * std::max<size_t>(tiles.size(), 1));   // may be empty
+    if (!t) return fail(LBM_ENOMEM, "tile table allocation failed");
+    hipError_t e = hipMemcpyAsync(t, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        dev_free(h, t);
+        return fail(LBM_EDEVICE, "tile table upload failed: %s", hipGetErrorString(e));
+    }
+    h->d_tiles = t;
     h->ntiles = (uint32_t)tiles.size();
     h->tiles_block = key;
     return LBM_OK;
@@ -558,7 +612,6 @@ static StepLaunch make_launch(lbm_handle* h, const lbm_launch& cfg, int parity) 
     s.collision = h->collision;
     s.block = cfg.block;
     s.cpl = cfg.cells_per_lane;
-    s.staged = cfg.staged;
     s.dense = cfg.mode == LBM_LAUNCH_DENSE ? 1 : 0;
     s.parity = parity;
     s.lats = h->d_lats;
@@ -572,9 +625,13 @@ static StepLaunch make_launch(lbm_handle* h, const lbm_launch& cfg, int parity) 
 }
 
 // Enqueue one time step with the given configuration, reading buffer `parity`.
+// Batched launches need the tile table (absent only after a failed rebuild).
 static hipError_t enqueue_step(lbm_handle* h, const lbm_launch& cfg, int parity) {
     const StepLaunch s = make_launch(h, cfg, parity);
-    if (cfg.mode != LBM_LAUNCH_PER_LATTICE) return s.ntiles ? launch_step_batched(s) : hipSuccess;
+    if (cfg.mode != LBM_LAUNCH_PER_LATTICE) {
+        if (!h->d_tiles) return hipErrorInvalidValue;
+        return s.ntiles ? launch_step_batched(s) : hipSuccess;
+    }
     for (auto& L : h->lats) {
         hipError_t e = launch_step_single(s, L.dev);
         if (e != hipSuccess) return e;
@@ -607,6 +664,9 @@ static lbm_status ensure_graph(lbm_handle* h) {
 extern "C" lbm_status lbm_step(lbm_handle* h, int64_t n) {
     if (!h) return fail(LBM_EINVAL, "handle is NULL");
     if (n < 0) return fail(LBM_EINVAL, "n_steps must be >= 0");
+    if (h->launch.mode != LBM_LAUNCH_PER_LATTICE && !h->d_tiles)
+        return fail(LBM_EINVAL, "no tile table for the batched launch (a previous call failed to build it); "
+                                "set the launch configuration again");
     lbm_status st = ensure_graph(h);
     if (st != LBM_OK) return st;
     const int K = h->graph ? h->graph_steps : 0;
@@ -663,9 +723,9 @@ extern "C" lbm_status lbm_set_boundaries(lbm_handle* h, int32_t k, const uint8_t
                            L.flags, L.near_bits, L.N, waves);
         e = hipGetLastError();
     }
+    if (e == hipSuccess) e = reset_nonfinite(h, k);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // fl is a local buffer
     dev_free(h, d_raw);
-    h->device_bytes -= (int64_t)L.N;
     if (e != hipSuccess) return fail(LBM_EDEVICE, "flag upload failed: %s", hipGetErrorString(e));
     drop_graph(h);
     L.host_flags.assign(flags, flags + L.N);
@@ -691,21 +751,22 @@ extern "C" lbm_status lbm_set_rho_u(lbm_handle* h, int32_t k, const double* rho,
     lbm_status st = check_lattice(h, k);
     if (st != LBM_OK) return st;
     Lattice& L = h->lats[k];
-    double* d_rho = nullptr;
-    double* d_u = nullptr;
-    if ((rho && hipMalloc(&d_rho, L.N * sizeof(double)) != hipSuccess) ||
-        (u && hipMalloc(&d_u, 3 * L.N * sizeof(double)) != hipSuccess)) {
-        (void)hipFree(d_rho);
+    double* d_rho = rho ? (double*)dev_alloc(h, L.N * sizeof(double)) : nullptr;
+    double* d_u = u ? (double*)dev_alloc(h, 3 * L.N * sizeof(double)) : nullptr;
+    if ((rho && !d_rho) || (u && !d_u)) {
+        dev_free(h, d_rho);
+        dev_free(h, d_u);
         return fail(LBM_ENOMEM, "rho/u upload buffers");
     }
     hipError_t e = hipSuccess;
     if (rho) e = hipMemcpyAsync(d_rho, rho, L.N * sizeof(double), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(d_u, u, 3 * L.N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = reset_nonfinite(h, k);
     st = e == hipSuccess ? run_init(h, L, d_rho, d_u) : LBM_OK;
     const hipError_t es = hipStreamSynchronize(h->stream);    // the uploads read the caller's buffers
     if (e == hipSuccess) e = es;
-    (void)hipFree(d_rho);
-    (void)hipFree(d_u);
+    dev_free(h, d_rho);
+    dev_free(h, d_u);
     if (st != LBM_OK) return st;
     if (e != hipSuccess) return fail(LBM_EDEVICE, "initialisation failed: %s", hipGetErrorString(e));
     h->step = 0;
@@ -716,13 +777,13 @@ extern "C" lbm_status lbm_get_rho_u(lbm_handle* h, int32_t k, double* rho, doubl
     lbm_status st = check_lattice(h, k);
     if (st != LBM_OK) return st;
     Lattice& L = h->lats[k];
-    double* d = nullptr;
-    if (hipMalloc(&d, 4 * L.N * sizeof(double)) != hipSuccess) return fail(LBM_ENOMEM, "moments buffer");
+    double* d = (double*)dev_alloc(h, 4 * L.N * sizeof(double));
+    if (!d) return fail(LBM_ENOMEM, "moments buffer");
     hipError_t e = launch_moments(h->q, h->storage, h->arith, L.dev, h->parity, d, d + L.N, h->stream);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d, L.N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(u, d + L.N, 3 * L.N * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    (void)hipFree(d);
+    dev_free(h, d);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "moments failed: %s", hipGetErrorString(e));
     return LBM_OK;
 }
@@ -738,6 +799,7 @@ extern "C" lbm_status lbm_set_ddf(lbm_handle* h, int32_t k, const void* host) {
         for (int i = 0; i < h->q; i++)
             HIP_TRY(hipMemcpyAsync((char*)L.f[buf] + (size_t)i * L.plane * b, (const char*)host + (size_t)i * L.N * b,
                                    L.N * b, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(reset_nonfinite(h, k));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
@@ -755,20 +817,27 @@ extern "C" lbm_status lbm_get_ddf(lbm_handle* h, int32_t k, void* host) {
     return LBM_OK;
 }
 
-extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_ref, lbm_diag* out) {
-    lbm_status st = check_lattice(h, k);
-    if (st != LBM_OK) return st;
-    if (!out) return fail(LBM_EINVAL, "out is NULL");
+// Workgroups of the first diagnostics pass over lattice L: one per row tile
+// of kDiagThreads cells, at most kDiagBlocks (they then stride over the tiles).
+static int diag_blocks(const Lattice& L, uint32_t* segs) {
+    *segs = (uint32_t)((L.p.nx + kDiagThreads - 1) / kDiagThreads);
+    const uint64_t tiles = (uint64_t)L.p.ny * (uint64_t)L.p.nz * *segs;
+    return (int)std::min<uint64_t>(tiles, (uint64_t)kDiagBlocks);
+}
+
+// Both passes of the FP64 diagnostics of lattice k (first-pass partials in
+// `partials`, at least kDiagBlocks * kDiagFields doubles; the kDiagFields
+// results in `res_dev`), then the results and the lattice's count of
+// non-finite updates to the host.  Synchronises.  d_ref: device u_ref or null.
+static lbm_status run_diagnostics(lbm_handle* h, int32_t k, const double* d_ref, double* partials,
+                                  double* res_dev, lbm_diag* out) {
     Lattice& L = h->lats[k];
-    double* d_ref = nullptr;
-    if (u_ref) {
-        if (hipMalloc(&d_ref, 3 * L.N * sizeof(double)) != hipSuccess) return fail(LBM_ENOMEM, "u_ref buffer");
-        hipError_t e = hipMemcpyAsync(d_ref, u_ref, 3 * L.N * sizeof(double), hipMemcpyHostToDevice, h->stream);
-        if (e != hipSuccess) { (void)hipFree(d_ref); return fail(LBM_EDEVICE, "u_ref upload failed"); }
-    }
+    uint32_t segs = 0;
+    const int nblocks = diag_blocks(L, &segs);
     double res[kDiagFields];
+    unsigned long long nonfinite_updates = 0;
     hipError_t e;
-#define E(N) diag_##N(h->q, h->arith, L.dev, h->parity, d_ref, h->d_partials, kDiagBlocks, h->stream)
+#define E(N) diag_##N(h->q, h->arith, L.dev, h->parity, d_ref, partials, nblocks, segs, h->stream)
     switch (h->storage) {
     case S_FP64: e = E(fp64); break;
     case S_FP32: e = E(fp32); break;
@@ -781,29 +850,53 @@ extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_
     }
 #undef E
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(64), 0, h->stream, h->d_partials, kDiagBlocks, h->d_out);
+        hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(256), 0, h->stream, partials, nblocks, res_dev);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(res, h->d_out, sizeof res, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(res, res_dev, sizeof res, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&nonfinite_updates, h->d_nonfinite + k, sizeof nonfinite_updates, hipMemcpyDeviceToHost,
+                           h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    (void)hipFree(d_ref);
     if (e != hipSuccess) return fail(LBM_EDEVICE, "diagnostics failed: %s", hipGetErrorString(e));
     out->mass = res[0];
     out->momentum[0] = res[1];
     out->momentum[1] = res[2];
     out->momentum[2] = res[3];
     out->kinetic_energy = res[4];
-    out->l2_error = u_ref ? (res[6] > 0 ? std::sqrt(res[5] / res[6]) : 0.0) : -1.0;
+    out->l2_error = d_ref ? (res[6] > 0 ? std::sqrt(res[5] / res[6]) : 0.0) : -1.0;
     out->force_on_solid[0] = res[7];
     out->force_on_solid[1] = res[8];
     out->force_on_solid[2] = res[9];
     out->nonfinite_cells = (int64_t)res[10];
-    out->u_max = res[11];
+    out->u_max = std::sqrt(res[11]);
     out->step = h->step;
-    if (out->nonfinite_cells > 0)
-        return fail(LBM_ENONFINITE, "lattice %d: %lld fluid cells with non-finite fields", k,
-                    (long long)out->nonfinite_cells);
+    out->nonfinite_updates = (int64_t)nonfinite_updates;
+    if (out->nonfinite_cells > 0 || out->nonfinite_updates > 0)
+        return fail(LBM_ENONFINITE, "lattice %d: %lld fluid cells with non-finite fields now, %lld cell updates "
+                    "with a non-finite density or velocity since the last initialisation", k,
+                    (long long)out->nonfinite_cells, (long long)out->nonfinite_updates);
     return LBM_OK;
+}
+
+extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_ref, lbm_diag* out) {
+    lbm_status st = check_lattice(h, k);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    Lattice& L = h->lats[k];
+    double* d_ref = nullptr;
+    if (u_ref) {
+        d_ref = (double*)dev_alloc(h, 3 * L.N * sizeof(double));
+        if (!d_ref) return fail(LBM_ENOMEM, "u_ref buffer");
+        const hipError_t e = hipMemcpyAsync(d_ref, u_ref, 3 * L.N * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) {
+            dev_free(h, d_ref);
+            return fail(LBM_EDEVICE, "u_ref upload failed: %s", hipGetErrorString(e));
+        }
+    }
+    st = run_diagnostics(h, k, d_ref, h->d_partials, h->d_out, out);
+    dev_free(h, d_ref);
+    return st;
 }
 
 // ------------------------------------------------------------------ launch configuration
@@ -811,32 +904,14 @@ static lbm_status check_launch(lbm_handle* h, const lbm_launch& c) {
     if (c.mode != LBM_LAUNCH_PER_LATTICE && c.mode != LBM_LAUNCH_BATCHED && c.mode != LBM_LAUNCH_DENSE)
         return fail(LBM_EINVAL, "unknown launch mode");
     if (c.block != 64 && c.block != 128 && c.block != 256 && c.block != 512) return fail(LBM_EINVAL, "block must be 64..512");
-    if (c.staged != 0 && c.staged != 1) return fail(LBM_EINVAL, "staged must be 0 or 1");
-    if (c.mode == LBM_LAUNCH_DENSE && (c.staged || c.cells_per_lane != 1))
-        return fail(LBM_EINVAL, "cell-contiguous tiles take one cell per lane and no staging");
-    if ((h->q != 19 && h->q != 27) && (c.staged || c.cells_per_lane != 1))
-        return fail(LBM_EUNSUPPORTED, "several cells per lane and the staged kernel are built for D3Q19 and D3Q27");
-    if (h->collision == LBM_MRT && (c.staged || c.cells_per_lane != 1))
-        return fail(LBM_EUNSUPPORTED, "MRT runs one cell per lane without staging");
-    if (c.staged) {
-        if (c.cells_per_lane != 1 && c.cells_per_lane != 2)
-            return fail(LBM_EINVAL, "the staged kernel takes 1 or 2 cells per thread");
-        if (staged_lds_bytes(h->q, h->storage, c.block, c.cells_per_lane) > 65536)
-            return fail(LBM_EUNSUPPORTED, "staged tile of %d cells does not fit 64 KiB of LDS",
-                        c.block * c.cells_per_lane);
-        const int ve = 16 / ddf_bytes(h->storage);
-        for (size_t k = 0; k < h->lats.size(); k++)
-            if (h->lats[k].p.nx % ve)
-                return fail(LBM_EINVAL, "lattice %zu: the staged kernel needs nx to be a multiple of %d", k, ve);
-        if (c.graph_steps < 0 || (c.graph_steps & 1) || c.graph_steps > 100000)
-            return fail(LBM_EINVAL, "graph_steps must be even and >= 0");
-        if (c.graph_steps > 0 && h->stream == nullptr)
-            return fail(LBM_EINVAL, "HIP graphs need a non-null stream (the null stream cannot be captured)");
-        if (c.persistent < 0 || c.persistent > 64) return fail(LBM_EINVAL, "persistent must be in [0, 64]");
-        return LBM_OK;
-    }
+    if (c.mode == LBM_LAUNCH_DENSE && c.cells_per_lane != 1)
+        return fail(LBM_EINVAL, "cell-contiguous tiles take one cell per lane");
     if (c.cells_per_lane != 1 && c.cells_per_lane != 2 && c.cells_per_lane != 4)
         return fail(LBM_EINVAL, "cells_per_lane must be 1, 2 or 4");
+    if ((h->q != 19 && h->q != 27) && c.cells_per_lane != 1)
+        return fail(LBM_EUNSUPPORTED, "several cells per lane are built for D3Q19 and D3Q27");
+    if (h->collision == LBM_MRT && c.cells_per_lane != 1)
+        return fail(LBM_EUNSUPPORTED, "MRT runs one cell per lane");
     if (c.cells_per_lane == 4 && ddf_bytes(h->storage) != 2)
         return fail(LBM_EUNSUPPORTED, "cells_per_lane 4 needs 16-bit storage");
     if (c.cells_per_lane > 1 && ddf_bytes(h->storage) == 8)
@@ -858,8 +933,18 @@ extern "C" lbm_status lbm_set_launch(lbm_handle* h, const lbm_launch* cfg) {
     lbm_status st = check_launch(h, *cfg);
     if (st != LBM_OK) return st;
     drop_graph(h);
+    const lbm_launch keep = h->launch;
     h->launch = *cfg;
-    return rebuild_tiles(h);
+    st = rebuild_tiles(h);
+    if (st != LBM_OK) {
+        // back to the previous configuration; should its table fail too,
+        // lbm_step refuses batched launches until a launch is set again
+        const std::string why = g_err;
+        h->launch = keep;
+        (void)rebuild_tiles(h);
+        g_err = why;
+    }
+    return st;
 }
 
 extern "C" lbm_status lbm_get_launch(lbm_handle* h, lbm_launch* cfg) {
@@ -874,18 +959,17 @@ extern "C" lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launc
     const lbm_launch keep = h->launch;
     std::vector<lbm_launch> cands;
     const int blocks[] = {64, 128, 256, 512};
-    for (int staged : {0, 1}) {
-        for (int cpl : {1, 2, 4}) {
-            for (int b : blocks) {
-                const lbm_launch c{LBM_LAUNCH_PER_LATTICE, b, cpl, staged, 0, keep.graph_steps};
-                if (check_launch(h, c) != LBM_OK) continue;
-                cands.push_back(c);
-                // persistent grids of half and full occupancy (2048 threads per CU)
-                const int pers[] = {0, 1024 / b, 2048 / b};
-                for (int pz : pers) {
-                    if (h->lats.size() > 1) cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, staged, pz, keep.graph_steps});
-                    if (cpl == 1 && !staged) cands.push_back({LBM_LAUNCH_DENSE, b, 1, 0, pz, keep.graph_steps});
-                }
+    // one or two cells per lane (four never won on the workloads measured)
+    for (int cpl : {1, 2}) {
+        for (int b : blocks) {
+            const lbm_launch c{LBM_LAUNCH_PER_LATTICE, b, cpl, 0, keep.graph_steps};
+            if (check_launch(h, c) != LBM_OK) continue;
+            cands.push_back(c);
+            // persistent grids of half and full occupancy (2048 threads per CU)
+            const int pers[] = {0, 1024 / b, 2048 / b};
+            for (int pz : pers) {
+                if (h->lats.size() > 1) cands.push_back({LBM_LAUNCH_BATCHED, b, cpl, pz, keep.graph_steps});
+                if (cpl == 1) cands.push_back({LBM_LAUNCH_DENSE, b, 1, pz, keep.graph_steps});
             }
         }
     }
@@ -915,8 +999,9 @@ extern "C" lbm_status lbm_autotune(lbm_handle* h, int32_t trial_steps, lbm_launc
         if (e != hipSuccess) {
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
+            drop_graph(h);
             h->launch = keep;
-            rebuild_tiles(h);
+            (void)rebuild_tiles(h);
             return fail(LBM_EDEVICE, "autotune launch failed: %s", hipGetErrorString(e));
         }
         // ties go to the smaller workgroup (candidates are in increasing size)

@@ -22,7 +22,7 @@ import json
 import os
 import tempfile
 
-LAUNCH_FIELDS = ("mode", "block", "cells_per_lane", "staged", "persistent")
+LAUNCH_FIELDS = ("mode", "block", "cells_per_lane", "persistent")
 
 
 def ensemble_key(params, device: str, library_id: str) -> str:

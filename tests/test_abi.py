@@ -35,15 +35,15 @@ def test_struct_layout_matches_header(tmp_path):
     import paper_2112_08926_amd as lbm
     src = tmp_path / "sizes.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\n'
-                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lbm_params),"
+                   "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lbm_params),"
                    " sizeof(lbm_diag), sizeof(lbm_launch), sizeof(lbm_info), offsetof(lbm_params, tau),"
-                   " offsetof(lbm_params, eq_u), offsetof(lbm_diag, nonfinite_cells));return 0;}\n")
+                   " offsetof(lbm_params, eq_u), offsetof(lbm_diag, nonfinite_cells), offsetof(lbm_diag, nonfinite_updates));return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     expect = [ctypes.sizeof(lbm.LbmParams), ctypes.sizeof(lbm.LbmDiag), ctypes.sizeof(lbm.LbmLaunch),
               ctypes.sizeof(lbm.LbmInfo), lbm.LbmParams.tau.offset, lbm.LbmParams.eq_u.offset,
-              lbm.LbmDiag.nonfinite_cells.offset]
+              lbm.LbmDiag.nonfinite_cells.offset, lbm.LbmDiag.nonfinite_updates.offset]
     assert got == expect
 
 

@@ -25,7 +25,7 @@ from lbm_testlib import TABLE, check_samples, model_walls, sample_points, say, s
 
 pytestmark = pytest.mark.gpu
 
-LAUNCH_FIELDS = ("mode", "block", "cells_per_lane", "staged", "persistent")
+LAUNCH_FIELDS = ("mode", "block", "cells_per_lane", "persistent")
 
 
 @pytest.fixture(scope="module")
@@ -44,10 +44,10 @@ def _arith(storage):
 # ------------------------------------------------------------ cavity 512^3
 N_CAV = 512
 CAVITY_EXTRA_CONFIGS = {
-    "fp16s": [("rows256", dict(mode=0, block=256, cells_per_lane=1, staged=0, persistent=0)),
-              ("dense256", dict(mode=2, block=256, cells_per_lane=1, staged=0, persistent=0)),
-              ("rows64_cpl2", dict(mode=0, block=64, cells_per_lane=2, staged=0, persistent=0))],
-    "fp32": [("rows256", dict(mode=0, block=256, cells_per_lane=1, staged=0, persistent=0))],
+    "fp16s": [("rows256", dict(mode=0, block=256, cells_per_lane=1, persistent=0)),
+              ("dense256", dict(mode=2, block=256, cells_per_lane=1, persistent=0)),
+              ("rows64_cpl2", dict(mode=0, block=64, cells_per_lane=2, persistent=0))],
+    "fp32": [("rows256", dict(mode=0, block=256, cells_per_lane=1, persistent=0))],
 }
 
 
@@ -118,9 +118,9 @@ def test_ensemble_full_sampled_parity_and_graph(lbm, orc):
             total += m
         say(f"  autotuned one step: {total} sampled fluid cells over {len(specs)} lattices")
         # 100 steps: persistent launch replayed as a HIP graph vs one launch per lattice
-        for name, cfg in [("per_lattice", dict(mode=0, block=128, cells_per_lane=1, staged=0, persistent=0,
+        for name, cfg in [("per_lattice", dict(mode=0, block=128, cells_per_lane=1, persistent=0,
                                                graph_steps=0)),
-                          ("persistent_graph100", dict(mode=2, block=256, cells_per_lane=1, staged=0,
+                          ("persistent_graph100", dict(mode=2, block=256, cells_per_lane=1,
                                                        persistent=8, graph_steps=100)),
                           ("autotuned_graph100", dict({k: best[k] for k in LAUNCH_FIELDS}, graph_steps=100))]:
             for k in range(len(specs)):

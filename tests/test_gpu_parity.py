@@ -234,17 +234,15 @@ def test_nonfinite_detected(lbm):
         assert d.nonfinite_cells >= 1
 
 
-@pytest.mark.parametrize("storage,cpl,staged,block", [
-    ("fp32", 2, 0, 64), ("fp16s", 2, 0, 64), ("fp16s", 4, 0, 64), ("fp16c", 4, 0, 64),
-    ("p16_1s", 2, 0, 64), ("p16_2c", 4, 0, 64), ("fp16", 4, 0, 64), ("p16_0s", 4, 0, 64),
-    ("fp16s", 1, 1, 64), ("fp16s", 2, 1, 128), ("fp16c", 2, 1, 64), ("fp32", 1, 1, 128),
-    ("fp32", 2, 1, 64), ("fp64", 1, 1, 64), ("p16_2c", 1, 1, 256), ("fp16", 2, 1, 64)])
+@pytest.mark.parametrize("storage,cpl,block", [
+    ("fp32", 2, 64), ("fp16s", 2, 64), ("fp16s", 4, 64), ("fp16c", 4, 64), ("p16_1s", 2, 64), ("p16_2c", 4, 64),
+    ("fp16", 4, 64), ("p16_0s", 4, 64), ("fp16s", 2, 128), ("fp16c", 2, 64), ("fp32", 2, 256), ("fp16", 2, 64)])
 @pytest.mark.parametrize("q,collision", [(19, "trt"), (27, "srt")])
-def test_cells_per_lane_bit_identical(lbm, orc, storage, cpl, staged, block, q, collision):
-    """Several cells per lane (vector loads, cross-lane shifts for +-x) and the
-    LDS-staged kernel give bit-identical states to one cell per lane, on a
-    ragged row (296 cells: several tiles plus a remainder) with walls, a
-    moving lid, EQ cells and a force, for several steps."""
+def test_cells_per_lane_bit_identical(lbm, orc, storage, cpl, block, q, collision):
+    """Several cells per lane (vector loads, cross-lane shifts for +-x) give
+    bit-identical states to one cell per lane, on a ragged row (296 cells:
+    several tiles plus a remainder) with walls, a moving lid, EQ cells and a
+    force, for several steps."""
     nx, ny, nz = 296, 5, 4
     say("cpl", storage, cpl, q, collision)
     flags, rho, u = one_step_inputs(nx, ny, nz, q, seed=29 + q)
@@ -253,18 +251,18 @@ def test_cells_per_lane_bit_identical(lbm, orc, storage, cpl, staged, block, q, 
     out = {}
     arith = "fp64" if storage == "fp64" else "fp32"
     kw["arith"] = arith
-    for c, blk, stg in ((1, 256, 0), (cpl, block, staged)):  # reference config first
+    for c, blk in ((1, 256), (cpl, block)):  # reference config first
         with lbm.Lattices(lbm.make_params(nx, ny, nz, **kw)) as g:
             g.set_boundaries(0, flags)
             g.set_rho_u(0, rho, u)
-            g.set_launch(block=blk, cells_per_lane=c, staged=stg)
+            g.set_launch(block=blk, cells_per_lane=c)
             first = None
             for _ in range(4):
                 g.step(1)
                 if first is None:
                     first = g.get_ddf(0)
             out[c] = (first, g.get_ddf(0))
-    key = (cpl, block, staged)
+    key = (cpl, block)
     assert np.array_equal(out[1][0], out[cpl][0]), key
     assert np.array_equal(out[1][1], out[cpl][1]), key
 
@@ -356,8 +354,6 @@ def test_invalid_launch_rejected(lbm):
         with pytest.raises(lbm.LbmError):
             g.set_launch(mode=2, cells_per_lane=2)   # cell-contiguous tiles: one cell per lane
         with pytest.raises(lbm.LbmError):
-            g.set_launch(mode=2, staged=1)
-        with pytest.raises(lbm.LbmError):
             g.set_launch(mode=3)
     with lbm.Lattices(lbm.make_params(32, 4, 4, storage="fp64", arith="fp64")) as g:
         with pytest.raises(lbm.LbmError):
@@ -419,37 +415,6 @@ def test_autotune_json_cache(lbm, tmp_path, monkeypatch):
         g.set_boundaries(0, flags)
         again = g.autotune(2, cache=cache)
         assert again["block"] != 7 and lbm.tuning.load(cache, key)["block"] == again["block"]
-
-
-def test_staged_batched_ensemble_bit_identical(lbm):
-    """Ensemble of lattices whose nx suit 16-byte rows: the LDS-staged kernel
-    in batched (one tile per workgroup and persistent) launches equals one
-    launch per lattice with one cell per lane."""
-    dims = [(32, 20, 9), (48, 11, 17), (72, 30, 5), (16, 8, 8)]
-    params, inputs = [], []
-    for k, (nx, ny, nz) in enumerate(dims):
-        spec = {"nx": nx, "ny": ny, "nz": nz, "tau": 0.6 + 0.1 * k,
-                "kind": "poiseuille" if k % 2 else "tgv", "u0": 0.05,
-                "R": min(ny, nz) // 2 - 1, "force": (1e-5, 0.0, 0.0) if k % 2 else (0.0, 0.0, 0.0)}
-        params.append(lbm.make_params(nx, ny, nz, storage="fp16s", collision="trt", tau=spec["tau"],
-                                      force=spec["force"]))
-        inputs.append(wl.ensemble_member_inputs(spec))
-    res = {}
-    for name, cfg in [("ref", dict(mode=0, block=64, cells_per_lane=1, staged=0)),
-                      ("staged", dict(mode=1, block=64, cells_per_lane=1, staged=1)),
-                      ("staged_pers", dict(mode=1, block=128, cells_per_lane=2, staged=1, persistent=2)),
-                      ("staged_graph", dict(mode=1, block=64, cells_per_lane=2, staged=1, graph_steps=2))]:
-        say("staged ensemble", name)
-        with lbm.Lattices(params) as g:
-            for k, (flags, rho, u) in enumerate(inputs):
-                g.set_boundaries(k, flags)
-                g.set_rho_u(k, rho, u)
-            g.set_launch(**cfg)
-            g.step(5)
-            res[name] = [g.get_ddf(k) for k in range(len(dims))]
-    for name in ("staged", "staged_pers", "staged_graph"):
-        for a, b in zip(res["ref"], res[name]):
-            assert np.array_equal(a, b), name
 
 
 def test_unshifted_fp64_matches_reference(lbm, orc):
@@ -605,8 +570,6 @@ def test_other_velocity_sets_rejected_where_not_built(lbm):
     with lbm.Lattices(lbm.make_params(32, 4, 4, q=15, storage="fp16s")) as g:
         with pytest.raises(lbm.LbmError):
             g.set_launch(cells_per_lane=2)
-        with pytest.raises(lbm.LbmError):
-            g.set_launch(staged=1)
 
 
 @pytest.mark.parametrize("storage", FORMATS)
@@ -661,5 +624,3 @@ def test_mrt_rejected_where_not_built(lbm):
     with lbm.Lattices(lbm.make_params(32, 4, 4, q=19, collision="mrt", storage="fp16s")) as g:
         with pytest.raises(lbm.LbmError):
             g.set_launch(cells_per_lane=2)
-        with pytest.raises(lbm.LbmError):
-            g.set_launch(staged=1)

@@ -58,7 +58,7 @@ def _run_mutant(tmp_path, k, name, old, new, text):
     so = tmp_path / f"libmutant{k}.so"
     subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                     "-o", str(so), str(src), "-lm"], check=True)
-    env = dict(os.environ, LBM_ORACLE_SO=str(so), OMP_NUM_THREADS="2")
+    env = dict(os.environ, LBM_ORACLE_SO=str(so), OMP_NUM_THREADS="2", OMP_WAIT_POLICY="passive")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *PINS],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     return name, r.returncode != 1, r.stdout[-1500:]

@@ -11,7 +11,7 @@ def _p(nx=64, ny=32, nz=16, q=19, collision=1, storage=3, arith=0, unshifted=0, 
                            unshifted=unshifted, tau=tau)
 
 
-LAUNCH = {"mode": 1, "block": 256, "cells_per_lane": 1, "staged": 0, "persistent": 2048, "graph_steps": 100}
+LAUNCH = {"mode": 1, "block": 256, "cells_per_lane": 1, "persistent": 2048, "graph_steps": 100}
 
 
 def test_key_is_stable_and_ignores_physics():
