@@ -292,26 +292,32 @@ def karman(storages=("fp16s", "fp16c", "fp32"), steps=50, warmup=10):
                         "tau 0.532 (Re 150)", "steps_from_start": steps + warmup + 2, "rows": rows}
 
 
-def copy_bandwidth(nbytes=4 << 30, reps=10):
-    """Achievable HBM bandwidth of a plain device copy (the library's copy
-    probe), counted as bytes read + bytes written."""
+def memory_bandwidths(nbytes=4 << 30, reps=10):
+    """Achievable HBM bandwidth of the library's memory microbenchmarks (the
+    paper's appendix memory benchmarks): a plain copy (bytes read + bytes
+    written) and coalesced / misaligned 4-byte reads and writes, each timed
+    over `reps` launches on 4 GiB buffers, in GB/s."""
     import torch
     import paper_2112_08926_amd as lbm
-    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")   # zero source: the read sink is never written
     b = torch.empty_like(a)
     stream = torch.cuda.current_stream()
-    lbm.lbm_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, stream)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        lbm.lbm_copy_probe(a.data_ptr(), b.data_ptr(), nbytes, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    out = {}
+    for kind in ("copy", "read", "read_misaligned", "write", "write_misaligned"):
+        lbm.lbm_memory_probe(kind, a.data_ptr(), b.data_ptr(), nbytes, stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            lbm.lbm_memory_probe(kind, a.data_ptr(), b.data_ptr(), nbytes, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        moved = 2 * nbytes if kind == "copy" else nbytes - (4 if kind.endswith("misaligned") else 0)
+        out[kind] = round(moved / (ms * 1e-3) / 1e9, 1)
     del a, b
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return out
 
 
 def accuracy_vs_fp64(formats, n=64, steps=1000):
@@ -410,8 +416,9 @@ def main():
               f"{results[s]['achieved_GBps']:.0f} GB/s, launch {results[s]['launch']}",
               file=sys.stderr, flush=True)
     head = results[HEADLINE]
-    print("[bench] copy probe", file=sys.stderr, flush=True)
-    copy_gbs = copy_bandwidth()
+    print("[bench] memory probes", file=sys.stderr, flush=True)
+    probes = memory_bandwidths()
+    copy_gbs = probes["copy"]
     acc = None
     if not args.no_accuracy:
         print("[bench] accuracy vs FP64 (64^3, 1000 steps)", file=sys.stderr, flush=True)
@@ -458,6 +465,7 @@ def main():
                     for s, r in results.items()},
         "fp16s_vs_fp32_speedup": (round(head["mlups"] / results["fp32"]["mlups"], 3)
                                   if "fp32" in results else None),
+        "memory_probes_GBps": probes,
         "l2_vs_fp64": acc,
         "ensemble": ens,
         "karman": kar,

@@ -275,6 +275,24 @@ lbm_status lbm_decode(int32_t storage, const uint16_t* d_in, float* d_out, int64
  * and achievable HBM bandwidth.  Asynchronous. */
 lbm_status lbm_copy_probe(const void* d_src, void* d_dst, size_t bytes, void* stream);
 
+/* Memory microbenchmarks of the paper's appendix (its memory benchmarks,
+ * Fig. 13, and the coalesced/misaligned read/write columns of Table 5): one
+ * kernel of the given kind over device buffers, one 4-byte element per
+ * thread (as a stream-collide kernel accesses DDFs).  Coalesced: element i at
+ * i; misaligned: at i + 1, so each wavefront's accesses straddle cache lines
+ * as the x-shifted pull reads do.  READ kinds read bytes/4 (- 1) elements of
+ * d_src and use d_dst (also `bytes` long) as a sink that is written only in
+ * the case, which the caller avoids, that the xor of a thread's elements is
+ * 0x9E3779B9 (all-zero sources are safe); WRITE kinds write
+ * d_dst[i (+ 1)] = i; COPY is lbm_copy_probe.  Bytes moved: the elements read
+ * or written (both for COPY).  Asynchronous.  LBM_EINVAL for an unknown kind,
+ * NULL or misaligned pointers, or sizes below 8 or not a multiple of 4. */
+typedef enum {
+    LBM_PROBE_COPY = 0, LBM_PROBE_READ = 1, LBM_PROBE_READ_MISALIGNED = 2,
+    LBM_PROBE_WRITE = 3, LBM_PROBE_WRITE_MISALIGNED = 4
+} lbm_probe_kind;
+lbm_status lbm_memory_probe(int32_t kind, const void* d_src, void* d_dst, size_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

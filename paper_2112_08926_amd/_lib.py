@@ -116,6 +116,7 @@ def library():
         "lbm_encode": (S, [ctypes.c_int32, _P, _P, ctypes.c_int64, _P]),
         "lbm_decode": (S, [ctypes.c_int32, _P, _P, ctypes.c_int64, _P]),
         "lbm_copy_probe": (S, [_P, _P, ctypes.c_size_t, _P]),
+        "lbm_memory_probe": (S, [ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -308,6 +309,13 @@ def lbm_decode(storage, d_in: int, d_out: int, n: int, stream=None):
 
 def lbm_copy_probe(d_src: int, d_dst: int, nbytes: int, stream=None):
     _check(library().lbm_copy_probe(d_src, d_dst, int(nbytes), _stream_ptr(stream)))
+
+
+PROBE = {"copy": 0, "read": 1, "read_misaligned": 2, "write": 3, "write_misaligned": 4}
+
+
+def lbm_memory_probe(kind, d_src: int | None, d_dst: int, nbytes: int, stream=None):
+    _check(library().lbm_memory_probe(PROBE.get(kind, kind), d_src, d_dst, int(nbytes), _stream_ptr(stream)))
 
 
 # ----------------------------------------------------------------- convenience wrapper

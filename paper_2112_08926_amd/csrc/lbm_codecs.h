@@ -32,9 +32,14 @@ __host__ __device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit
 // 1 sign | 4 exponent (bias 15) | 11 mantissa, no Inf/NaN.  Placing the 15
 // magnitude bits at FP32 bits 26..12 gives 2^(e-127)(1 + m/2^11), or the FP32
 // denormal m 2^-137 for e = 0; one multiply by 2^112 rebiases both exactly.
+// From the sign-extended code (what a sign-extending 16-bit load gives):
+// shifted by 12, its bits 31..27 are all the sign, so one mask keeps the sign
+// at bit 31 and the magnitude at bits 26..12.
+__host__ __device__ __forceinline__ float fp16c_decode_sext(int32_t cs) {
+    return u2f(((uint32_t)cs << 12) & 0x87FFF000u) * 0x1p112f;
+}
 __host__ __device__ __forceinline__ float fp16c_decode(uint32_t c) {
-    const uint32_t bits = ((c & 0x8000u) << 16) | ((c & 0x7FFFu) << 12);
-    return u2f(bits) * 0x1p112f;
+    return fp16c_decode_sext((int32_t)(int16_t)(uint16_t)c);
 }
 
 // Nearest FP16C code, ties away from zero, saturating at 0x7FFF (NaN too).
@@ -181,7 +186,7 @@ template <> struct Codec<S_FP16C> : RawCodec<S_FP16C> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = false;            // arithmetic encoder
-    template <class A> __device__ __forceinline__ static A load(T v) { return fp16c_decode(v); }
+    template <class A> __device__ __forceinline__ static A load(T v) { return fp16c_decode_sext((int16_t)v); }
     template <class A> __device__ __forceinline__ static T store(A v, const EncEntry*) { return fp16c_encode(v); }
 };
 template <> struct Codec<S_P16_0S> : RawCodec<S_P16_0S> {

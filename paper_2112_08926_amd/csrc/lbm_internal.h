@@ -85,8 +85,7 @@ hipError_t launch_eq_codes(int q, int storage, int arith, const LatDev& lat, voi
     hipError_t eq_codes_##NAME(int q, int arith, const LatDev& lat, void* out,               \
                                const EncEntry* enc, hipStream_t st);                         \
     hipError_t diag_##NAME(int q, int arith, const LatDev& lat, int parity,                  \
-                           const double* u_ref, double* partials, int nblocks, uint32_t segs,   \
-                           hipStream_t st);
+                           const double* u_ref, double* partials, uint32_t segs, hipStream_t st);
 LBM_DECLARE_FORMAT(fp64)
 LBM_DECLARE_FORMAT(fp32)
 LBM_DECLARE_FORMAT(fp16)
@@ -97,8 +96,8 @@ LBM_DECLARE_FORMAT(p16_1s)
 LBM_DECLARE_FORMAT(p16_2c)
 #undef LBM_DECLARE_FORMAT
 
-constexpr int kDiagBlocks = 2048;   // most workgroups of the first diagnostics pass (8 per CU)
-constexpr int kDiagThreads = 256;   // threads per workgroup of the first pass = cells per row tile
+constexpr int kDiagThreads = 512;   // threads per workgroup of the first pass = cells per row tile
 constexpr int kDiagFields = 12;     // mass, mom x3, ke, err2, ref2, force x3, nonfinite, max |u|^2
+constexpr int kDiagReduceBlocks = 512;  // workgroups of the second pass (each a fixed range of tiles)
 
 }  // namespace lbm

@@ -180,6 +180,13 @@ __device__ __forceinline__ void st_off(T* base, uint32_t idx, T v) {
     __builtin_nontemporal_store(v, (LBM_GLOBAL T*)((LBM_GLOBAL char*)base + (uint32_t)(idx * (uint32_t)sizeof(T))));
 }
 
+// 2^e for e >= 0, exactly, at compile time.
+constexpr double exp2i(int e) {
+    double r = 1.0;
+    for (int k = 0; k < e; k++) r *= 2.0;
+    return r;
+}
+
 // RAW: values in the storage's raw units (2^-kRawExp), as the step uses them;
 // otherwise physical values (moments and diagnostics).
 template <int Q, int F, class A, bool RAW>
@@ -188,7 +195,7 @@ __device__ __forceinline__ A load_ddf(typename Codec<F>::T v) {
     else return Codec<F>::template load<A>(v);
 }
 template <int F, bool RAW>
-constexpr double raw_scale() { return RAW ? (double)(1u << Codec<F>::kRawExp) : 1.0; }
+constexpr double kRawScale = RAW ? exp2i(Codec<F>::kRawExp) : 1.0;   // a constant: evaluated at compile time
 
 // Whether a wavefront whose cells lie in n_first .. n_first + 63 holds a cell
 // with a wall source: bits g and g + 1 (g = n_first / 64) of the lattice's
@@ -260,7 +267,7 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
                 if (fs & F_MOVING) {
                     const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                      VelSet<Q>::c[i][2] * L.wall_u[2]);
-                    f[i] += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, RAW>()) * cu;
+                    f[i] += (A)(6.0 * VelSet<Q>::w(i) * kRawScale<F, RAW>) * cu;
                 }
             }
         }
@@ -427,7 +434,7 @@ template <class A, int E>
 __device__ __forceinline__ void collide_mrt(A w, A rho, A rhom1, A C, A u3x, A u3y, A u3z, A ux, A uy, A uz,
                                             A Fx, A Fy, A Fz, A uF, bool forced, const A (&f)[19], A feq0,
                                             A (&fo)[19]) {
-    constexpr double kSc = (double)(1u << E);
+    constexpr double kSc = exp2i(E);
     const A sc = (A)kSc;
     A d[19];
     d[0] = f[0] - feq0;
@@ -479,7 +486,7 @@ __device__ __forceinline__ void collide_mrt(A w, A rho, A rhom1, A C, A u3x, A u
 template <int Q, int COLL, class A, bool EXACT_DIV, int E>
 __device__ __forceinline__ void collide(const LatDev& L, const A (&f)[Q], A (&fo)[Q], bool& bad) {
     static_assert(!EXACT_DIV || E == 0, "scaled units only with the reciprocal path");
-    constexpr double kSc = (double)(1u << E);
+    constexpr double kSc = exp2i(E);
     const A sc = (A)kSc;
     A j[3];
     const A r = fields_sum<Q, A>(f);                         // raw units
@@ -644,13 +651,14 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
 
     // The DDF loads go out together with the flag load (every address is in
     // the lattice whatever the flag), so a wavefront waits for memory once;
-    // wall and EQ cells load and decode too and then store what they keep.
+    // wall and EQ cells load, decode and collide too (on the finite values
+    // their sources hold) and then store what they keep instead.
     A f[Q], fo[Q];
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
     pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
-    bool bad = false;
-    if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
-    count_nonfinite(L, bad);
+    bool bad;
+    collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
+    count_nonfinite(L, bad && !special);
     T eq[Q];
     eq_codes_if<Q, F>(L, __any((fl & F_EQ) != 0), eq);
     const size_t plane = L.plane;
@@ -700,9 +708,9 @@ __device__ __forceinline__ void step_tile_dense(const LatDev& L, uint32_t x0, ui
     A f[Q], fo[Q];
     pull<Q, F, A, true, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);   // loads with the flag's
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
-    bool bad = false;
-    if (!special) collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
-    count_nonfinite(L, bad);
+    bool bad;
+    collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);   // all lanes: fo always defined
+    count_nonfinite(L, bad && !special);
     T eq[Q];
     eq_codes_if<Q, F>(L, __any((fl & F_EQ) != 0), eq);
     const size_t plane = L.plane;
@@ -943,7 +951,7 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
                         if (fs & F_MOVING) {
                             const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
                                              VelSet<Q>::c[i][2] * L.wall_u[2]);
-                            v += (A)(6.0 * VelSet<Q>::w(i) * raw_scale<F, true>()) * cu;
+                            v += (A)(6.0 * VelSet<Q>::w(i) * kRawScale<F, true>) * cu;
                         }
                     }
                     f[i] = v;
@@ -1139,64 +1147,168 @@ __global__ void __launch_bounds__(256) k_moments(LatDev L, int parity, double* _
 }
 
 // ------------------------------------------------------------ FP64 diagnostics
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// Sum (or max) of a double over each row of 16 lanes with DPP moves (no LDS):
+// xor 1 and xor 2 inside quads, then the mirrored half rows and rows; every
+// lane of a row ends with the row's result, combined in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
 }
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64_rows(double v) {      // rows outside ROWS read 0
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
+}
+// Sum (or max, of non-negative values) of a double over the wavefront, in a
+// fixed order: rows of 16 lanes first (xor 1, xor 2, mirrored half rows,
+// mirrored rows), then lane 15 of rows 0 and 2 into rows 1 and 3, then lane
+// 31 into rows 2 and 3; lane 63 ends with the result.
+template <bool MAX>
+__device__ __forceinline__ double wave_reduce(double v) {
+    constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140, kBcast15 = 0x142,
+                  kBcast31 = 0x143;
+    v = MAX ? fmax(v, dpp_f64<kXor1>(v)) : v + dpp_f64<kXor1>(v);
+    v = MAX ? fmax(v, dpp_f64<kXor2>(v)) : v + dpp_f64<kXor2>(v);
+    v = MAX ? fmax(v, dpp_f64<kHalfMirror>(v)) : v + dpp_f64<kHalfMirror>(v);
+    v = MAX ? fmax(v, dpp_f64<kMirror>(v)) : v + dpp_f64<kMirror>(v);
+    v = MAX ? fmax(v, dpp_f64_rows<kBcast15, 0xA>(v)) : v + dpp_f64_rows<kBcast15, 0xA>(v);
+    v = MAX ? fmax(v, dpp_f64_rows<kBcast31, 0xC>(v)) : v + dpp_f64_rows<kBcast31, 0xC>(v);
     return v;
 }
 
-// Block-wide reduction of kDiagFields values (the last one by max) in a fixed
-// order; thread 0 writes them to out.
-__device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], double* out) {
-    __shared__ double s[kDiagFields][16];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+// Block-wide reduction of kDiagFields values (the last one by max, of
+// non-negative values) in a fixed order, without a barrier at the end: each
+// wavefront reduces its values with DPP and puts them in its LDS slot
+// (fields absent in the wavefront -- bit k of the wavefront-uniform `skip`
+// -- as 0), then counts itself in; the wavefront that counts last sums the
+// slots in wavefront order (lane k field k) and writes out[k].  The others
+// leave as soon as they have counted, instead of waiting for the slowest.
+// `count` must be zero at entry for the whole workgroup (set before a
+// barrier at the start of the kernel).
+__device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], uint32_t skip, double* out,
+                                                   uint32_t* count) {
+    constexpr int kMaxWaves = 1024 / 64;
+    __shared__ double s[kDiagFields][kMaxWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
 #pragma unroll
     for (int k = 0; k < kDiagFields; k++) {
-        const double v = (k == kDiagFields - 1) ? wave_max(acc[k]) : wave_sum(acc[k]);
-        if (lane == 0) s[k][wid] = v;
+        double v = 0.0;
+        if (!((skip >> k) & 1u)) v = k == kDiagFields - 1 ? wave_reduce<true>(acc[k]) : wave_reduce<false>(acc[k]);
+        if (lane == 63) s[k][wave] = v;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < kDiagFields; k++) {
-            double v = s[k][0];
-            for (int w = 1; w < nw; w++) v = (k == kDiagFields - 1) ? fmax(v, s[k][w]) : v + s[k][w];
-            out[k] = v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint32_t before = 0;
+    if (lane == 0) before = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    before = (uint32_t)__builtin_amdgcn_readfirstlane((int)before);
+    if (before != (uint32_t)nwaves - 1) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lane < kDiagFields) {
+        double v = s[lane][0];
+        for (int w = 1; w < nwaves; w++) v = (lane == kDiagFields - 1) ? fmax(v, s[lane][w]) : v + s[lane][w];
+        out[lane] = v;
+    }
+}
+
+// The FP64 contributions of one fluid cell (flags fl) whose pulled DDFs are
+// f, added to v: mass, momentum, kinetic energy, the error norms against
+// u_ref, the momentum exchange into walls, the non-finite count and the
+// largest |u|^2.  The moments are those the next step sees after streaming
+// (velocity with F/2, not clamped), in the step's arithmetic.
+template <int Q, int F, class A>
+__device__ __forceinline__ void diag_cell(const LatDev& L, const typename Codec<F>::T* __restrict__ src, uint32_t fl,
+                                          uint32_t x, uint32_t y, uint32_t z, uint32_t n, const A (&f)[Q],
+                                          const double* __restrict__ u_ref, double (&v)[kDiagFields]) {
+    if (fl & (F_SOLID | F_EQ)) return;
+    A rho, j[3];
+    fields<Q, A>(f, (A)L.shift, rho, j);
+    if (L.forced) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) j[a] += (A)0.5 * (A)L.force[a];
+    }
+    const A inv = (A)1 / rho;                                    // one division, three products
+    const double r = (double)rho, ux = (double)(j[0] * inv), uy = (double)(j[1] * inv), uz = (double)(j[2] * inv);
+    if (!(isfinite(r) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
+        v[10] += 1.0;
+        return;
+    }
+    v[0] += r;
+    v[1] += r * ux;
+    v[2] += r * uy;
+    v[3] += r * uz;
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    v[4] += 0.5 * r * u2;
+    v[11] = fmax(v[11], u2);
+    if (u_ref) {
+        const size_t N = (size_t)L.nx * L.ny * L.nz;
+        const double rx = u_ref[n], ry = u_ref[N + n], rz = u_ref[2 * N + n];
+        v[5] += (ux - rx) * (ux - rx) + (uy - ry) * (uy - ry) + (uz - rz) * (uz - rz);
+        v[6] += rx * rx + ry * ry + rz * rz;
+    }
+    if (fl & F_NEAR) {
+        // momentum exchange: every link to a wall source x - c_i carries
+        // c_opp (2 (f*_opp + w_opp) + 6 w_i c_i.u_w) into the wall, f*_opp
+        // being what this cell sent towards the wall in the last step.  A
+        // loop, not unrolled (few cells take it); the source cell is found
+        // from the direction's components, so no array of the row context is
+        // indexed at run time (that would put it in scratch memory).
+        const size_t plane = L.plane;
+        const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
+        const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+        const uint32_t m = ld_mask(L.wall_mask, n);
+#pragma unroll 1
+        for (int i = 1; i < Q; i++) {
+            if (!((m >> i) & 1u)) continue;
+            const int o = opp(i);
+            const int cx = VelSet<Q>::c[i][0], cy = VelSet<Q>::c[i][1], cz = VelSet<Q>::c[i][2];
+            const double fo = (double)load_ddf<Q, F, A, false>(ld_off(src + (size_t)o * plane, n)) +
+                              VelSet<Q>::w(o) * L.shift;
+            double mv = 0.0;
+            if (m & 0x80000000u) {
+                const uint32_t sx = cx > 0 ? xm : (cx < 0 ? xp : x);
+                const uint32_t sy = wrap_add(y, -cy, L.ny), sz = wrap_add(z, -cz, L.nz);
+                const uint8_t fs = ld_off(L.flags, sx + (sy + sz * L.ny) * L.nx);
+                if (fs & F_MOVING) mv = 6.0 * VelSet<Q>::w(i) * (cx * L.wall_u[0] + cy * L.wall_u[1] + cz * L.wall_u[2]);
+            }
+            const double t = 2.0 * fo + mv;                         // c_opp = -c_i
+            v[7] -= cx * t;
+            v[8] -= cy * t;
+            v[9] -= cz * t;
         }
     }
 }
 
-// First pass.  The lattice is cut into row tiles of kDiagThreads cells (segs
-// per row, the step's decomposition: one scalar division per tile for the
-// row's y and z, neighbour rows and wrap workgroup-uniform, the wall mask
-// read only by wavefronts next to a wall).  Workgroup b takes the tiles
-// b, b + G, b + 2G, ... of a fixed grid of G workgroups, so every lane sums
-// its cells in a fixed order and the result does not depend on timing.
-// Accumulators per lane, in FP64: mass, momentum (3), kinetic energy, error
-// and reference norms, the momentum exchange into walls (3), non-finite
-// cells, and the largest |u|^2 (its square root is taken once, at the end).
-// The moments are those the next step sees after streaming (velocity with
-// F/2, not clamped), in the arithmetic precision of the step.
+// First pass: the step's decomposition, one workgroup per row tile of
+// kDiagThreads cells (grid (ny, segs, nz): the row's y and z are the block
+// indices, neighbour rows and wrap workgroup-uniform, the wall mask read only
+// by wavefronts next to a wall), one cell per lane.  The workgroup's FP64
+// sums, in a fixed order, go to partials[tile] (tile = (z ny + y) segs +
+// segment), which the fixed-order passes of k_diag_reduce sum, so repeated
+// calls give identical results.  The largest |u|^2 is reduced by max; its
+// square root is taken once, at the end.  Nothing is carried from one cell to
+// the next and the workgroup's wavefronts leave without waiting for each
+// other, which keeps the kernel's occupancy and its wavefronts' lifetimes
+// close to the step's.  (Two rows per workgroup, with both cells' loads in
+// flight, was slower: the extra registers cost more wavefronts than the
+// second cell gained.)
 template <int Q, int F, class A>
 __global__ void __launch_bounds__(kDiagThreads) k_diag(LatDev L, int parity, const double* __restrict__ u_ref,
                                                        double* __restrict__ partials, uint32_t segs) {
     using T = typename Codec<F>::T;
-    const uint32_t N = L.nx * L.ny * L.nz;                   // < 2^31
-    const uint32_t ntiles = L.ny * L.nz * segs;              // <= N + ny nz < 2^32
-    double acc[kDiagFields];
+    __shared__ uint32_t waves_done;
+    if (threadIdx.x == 0) waves_done = 0;
+    __syncthreads();
+    const uint32_t y = blockIdx.x, seg = blockIdx.y, z = blockIdx.z;
+    const uint32_t x = seg * kDiagThreads + threadIdx.x;
+    double v[kDiagFields];
 #pragma unroll
-    for (int k = 0; k < kDiagFields; k++) acc[k] = 0.0;
-    const T* __restrict__ src = (const T*)L.f[parity];
-    const size_t plane = L.plane;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint32_t row = t / segs;                       // workgroup-uniform
-        const uint32_t x = (t - row * segs) * kDiagThreads + threadIdx.x;
-        if (x >= L.nx) continue;
-        const uint32_t y = row % L.ny, z = row / L.ny;
+    for (int k = 0; k < kDiagFields; k++) v[k] = 0.0;
+    if (x < L.nx) {
+        const T* __restrict__ src = (const T*)L.f[parity];
         RowCtx rc;
         make_rows(L, y, z, rc);
         const uint32_t n = rc.rows[4] + x;
@@ -1205,57 +1317,15 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(LatDev L, int parity, con
         const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
         A f[Q];
         pull<Q, F, A, false>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
-        if (fl & (F_SOLID | F_EQ)) continue;
-        A rho, j[3];
-        fields<Q, A>(f, (A)L.shift, rho, j);
-        if (L.forced) {
-#pragma unroll
-            for (int a = 0; a < 3; a++) j[a] += (A)0.5 * (A)L.force[a];
-        }
-        const double r = (double)rho, ux = (double)(j[0] / rho), uy = (double)(j[1] / rho),
-                     uz = (double)(j[2] / rho);
-        if (!(isfinite(r) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
-            acc[10] += 1.0;
-            continue;
-        }
-        acc[0] += r;
-        acc[1] += r * ux;
-        acc[2] += r * uy;
-        acc[3] += r * uz;
-        const double u2 = ux * ux + uy * uy + uz * uz;
-        acc[4] += 0.5 * r * u2;
-        acc[11] = fmax(acc[11], u2);
-        if (u_ref) {
-            const double rx = u_ref[n], ry = u_ref[(size_t)N + n], rz = u_ref[2 * (size_t)N + n];
-            acc[5] += (ux - rx) * (ux - rx) + (uy - ry) * (uy - ry) + (uz - rz) * (uz - rz);
-            acc[6] += rx * rx + ry * ry + rz * rz;
-        }
-        if (fl & F_NEAR) {
-            // momentum exchange: every link to a wall source x - c_i carries
-            // c_opp (2 (f*_opp + w_opp) + 6 w_i c_i.u_w) into the wall, f*_opp
-            // being what this cell sent towards the wall in the last step
-            const uint32_t m = ld_mask(L.wall_mask, n);
-#pragma unroll 1
-            for (int i = 1; i < Q; i++) {
-                if (!((m >> i) & 1u)) continue;
-                const int o = opp(i);
-                const double fo = (double)load_ddf<Q, F, A, false>(ld_off(src + (size_t)o * plane, n)) +
-                                  VelSet<Q>::w(o) * L.shift;
-                double mv = 0.0;
-                if (m & 0x80000000u) {
-                    const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
-                    if (fs & F_MOVING)
-                        mv = 6.0 * VelSet<Q>::w(i) *
-                             (VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
-                              VelSet<Q>::c[i][2] * L.wall_u[2]);
-                }
-                acc[7] += VelSet<Q>::c[o][0] * (2.0 * fo + mv);
-                acc[8] += VelSet<Q>::c[o][1] * (2.0 * fo + mv);
-                acc[9] += VelSet<Q>::c[o][2] * (2.0 * fo + mv);
-            }
-        }
+        diag_cell<Q, F, A>(L, src, fl, x, y, z, n, f, u_ref, v);
     }
-    block_reduce_store(acc, partials + (size_t)blockIdx.x * kDiagFields);
+    // fields no cell of this wavefront has: the reference norms without u_ref,
+    // the wall force away from walls, the non-finite count if all are finite
+    uint32_t skip = 0;
+    if (!u_ref) skip |= (1u << 5) | (1u << 6);
+    if (!__any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0)) skip |= (1u << 7) | (1u << 8) | (1u << 9);
+    if (!__any(v[10] != 0.0)) skip |= 1u << 10;
+    block_reduce_store(v, skip, partials + ((size_t)(z * L.ny + y) * segs + seg) * kDiagFields, &waves_done);
 }
 
 // ------------------------------------------------------------ host launchers

@@ -128,19 +128,22 @@ hipError_t launch_eq_codes(int q, int storage, int arith, const LatDev& lat, voi
 }  // namespace lbm
 
 // ------------------------------------------------------------------ small kernels
-// Second pass of the diagnostics: one workgroup of 256 threads sums the
-// first pass's per-workgroup partials (the last field by max) in a fixed
-// order -- thread t the partials t, t + 256, ..., then a fixed tree -- so
-// repeated calls give identical results.
-__global__ void __launch_bounds__(256) k_diag_finish(const double* __restrict__ partials, int nblocks,
+// Later passes of the diagnostics: workgroup b sums the partials
+// b*chunk .. min((b+1)*chunk, count) - 1 (the last field by max) into out[b],
+// thread t the partials t, t + 256, ... of that range, then a fixed tree, so
+// repeated calls give identical results.  Run with many workgroups over the
+// first pass's partials, then with one workgroup over theirs.
+__global__ void __launch_bounds__(256) k_diag_reduce(const double* __restrict__ in, uint32_t count, uint32_t chunk,
                                                      double* __restrict__ out) {
     __shared__ double s[kDiagFields][256];
     const int t = threadIdx.x;
+    const uint32_t begin = blockIdx.x * chunk;
+    const uint32_t end = min(begin + chunk, count);
 #pragma unroll
     for (int k = 0; k < kDiagFields; k++) {
         double v = 0.0;
-        for (int b = t; b < nblocks; b += 256) {
-            const double p = partials[(size_t)b * kDiagFields + k];
+        for (uint32_t b = begin + t; b < end; b += 256) {
+            const double p = in[(size_t)b * kDiagFields + k];
             v = (k == kDiagFields - 1) ? fmax(v, p) : v + p;
         }
         s[k][t] = v;
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(256) k_diag_finish(const double* __restrict__ 
         }
         __syncthreads();
     }
-    if (t < kDiagFields) out[t] = s[t][0];
+    if (t < kDiagFields) out[(size_t)blockIdx.x * kDiagFields + t] = s[t][0];
 }
 
 __global__ void __launch_bounds__(256) k_encode(int storage, const float* __restrict__ in,
@@ -257,6 +260,27 @@ __global__ void __launch_bounds__(256) k_copy(const f32x4* __restrict__ src, f32
         __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Memory microbenchmarks (the paper's appendix, Fig. 13: coalesced and
+// misaligned reads and writes, one 4-byte element per lane as the DDF
+// accesses of a stream-collide kernel).  Misaligned: the element index is
+// shifted by one, so every wavefront's 256 bytes straddle two 128-byte
+// lines, as the x-shifted pull reads of the step do.  Reads accumulate their
+// elements (xor) and write one word per lane only if it equals a value the
+// caller never stores, so the loads cannot be dropped and nothing is
+// written in practice.  A thread that reads nothing keeps acc = 0 and
+// writes nothing, so sink indices stay below n.
+__global__ void __launch_bounds__(256) k_mem_read(const uint32_t* __restrict__ src, uint32_t* __restrict__ sink,
+                                                  size_t n, uint32_t shift) {
+    uint32_t acc = 0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        acc ^= src[i + shift];
+    if (acc == 0x9E3779B9u) sink[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+__global__ void __launch_bounds__(256) k_mem_write(uint32_t* __restrict__ dst, size_t n, uint32_t shift) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i + shift] = (uint32_t)i;
+}
+
 // ------------------------------------------------------------------ handle
 struct Lattice {
     lbm_params p{};
@@ -304,15 +328,32 @@ struct lbm_handle {
     // graph
     hipGraphExec_t graph = nullptr;
     int graph_steps = 0;
-    // diagnostics scratch
+    // diagnostics: partials and results of the reduction (largest lattice)
     double* d_partials = nullptr;
-    double* d_out = nullptr;
     // per lattice: cell updates with a non-finite density or velocity before
     // the clamp since the lattice was last initialised
     unsigned long long* d_nonfinite = nullptr;
     // size of every device allocation the handle holds (for device_bytes)
     std::unordered_map<void*, size_t> sizes;
 };
+
+// Reduction layout of lattice L: `tiles` first-pass partials (one per row
+// tile of kDiagThreads cells, segs per row), `groups` second-pass partials,
+// then the results; diag_doubles() is the scratch this needs.
+struct DiagLayout {
+    uint32_t segs, tiles, groups, chunk;
+};
+static DiagLayout diag_layout(const Lattice& L) {
+    DiagLayout d;
+    d.segs = (uint32_t)((L.p.nx + kDiagThreads - 1) / kDiagThreads);
+    d.tiles = (uint32_t)L.p.ny * (uint32_t)L.p.nz * d.segs;
+    d.groups = std::min<uint32_t>(d.tiles, kDiagReduceBlocks);
+    d.chunk = (d.tiles + d.groups - 1) / d.groups;
+    return d;
+}
+static size_t diag_doubles(const DiagLayout& d) {
+    return ((size_t)d.tiles + d.groups + 1) * kDiagFields;
+}
 
 // Device memory of a handle, through the caller's allocator hooks if given.
 // Every allocation the library makes for a handle goes through here, also
@@ -497,10 +538,11 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
         st = run_init(h, L, nullptr, nullptr);
         if (st != LBM_OK) { lbm_destroy(h); return st; }
     }
-    h->d_partials = (double*)dev_alloc(h, sizeof(double) * kDiagBlocks * kDiagFields);
-    h->d_out = (double*)dev_alloc(h, sizeof(double) * kDiagFields);
+    size_t diag_work = 0;
+    for (const Lattice& L : h->lats) diag_work = std::max(diag_work, diag_doubles(diag_layout(L)));
+    h->d_partials = (double*)dev_alloc(h, sizeof(double) * diag_work);
     h->d_lats = (LatDev*)dev_alloc(h, sizeof(LatDev) * n_lattices);
-    if (!h->d_partials || !h->d_out || !h->d_lats) {
+    if (!h->d_partials || !h->d_lats) {
         lbm_destroy(h);
         return fail(LBM_ENOMEM, "device allocation failed");
     }
@@ -531,7 +573,6 @@ extern "C" void lbm_destroy(lbm_handle* h) {
         dev_free(h, L.eq_codes);
     }
     dev_free(h, h->d_partials);
-    dev_free(h, h->d_out);
     dev_free(h, h->d_lats);
     dev_free(h, h->d_tiles);
     dev_free(h, h->d_nonfinite);
@@ -817,27 +858,21 @@ extern "C" lbm_status lbm_get_ddf(lbm_handle* h, int32_t k, void* host) {
     return LBM_OK;
 }
 
-// Workgroups of the first diagnostics pass over lattice L: one per row tile
-// of kDiagThreads cells, at most kDiagBlocks (they then stride over the tiles).
-static int diag_blocks(const Lattice& L, uint32_t* segs) {
-    *segs = (uint32_t)((L.p.nx + kDiagThreads - 1) / kDiagThreads);
-    const uint64_t tiles = (uint64_t)L.p.ny * (uint64_t)L.p.nz * *segs;
-    return (int)std::min<uint64_t>(tiles, (uint64_t)kDiagBlocks);
-}
-
-// Both passes of the FP64 diagnostics of lattice k (first-pass partials in
-// `partials`, at least kDiagBlocks * kDiagFields doubles; the kDiagFields
-// results in `res_dev`), then the results and the lattice's count of
-// non-finite updates to the host.  Synchronises.  d_ref: device u_ref or null.
-static lbm_status run_diagnostics(lbm_handle* h, int32_t k, const double* d_ref, double* partials,
-                                  double* res_dev, lbm_diag* out) {
+// The FP64 diagnostics of lattice k: the first pass, the two reduction
+// passes, then the results and the lattice's count of non-finite updates to
+// the host.  `work`: device memory of at least diag_doubles() doubles for
+// the partials and results.  Synchronises.  d_ref: device u_ref or null.
+static lbm_status run_diagnostics(lbm_handle* h, int32_t k, const double* d_ref, double* work, lbm_diag* out) {
     Lattice& L = h->lats[k];
-    uint32_t segs = 0;
-    const int nblocks = diag_blocks(L, &segs);
+    const DiagLayout dl = diag_layout(L);
+    double* partials = work;
+    double* groups = work + (size_t)dl.tiles * kDiagFields;
+    double* res_dev = groups + (size_t)dl.groups * kDiagFields;
+    const uint32_t segs = dl.segs;
     double res[kDiagFields];
     unsigned long long nonfinite_updates = 0;
     hipError_t e;
-#define E(N) diag_##N(h->q, h->arith, L.dev, h->parity, d_ref, partials, nblocks, segs, h->stream)
+#define E(N) diag_##N(h->q, h->arith, L.dev, h->parity, d_ref, partials, segs, h->stream)
     switch (h->storage) {
     case S_FP64: e = E(fp64); break;
     case S_FP32: e = E(fp32); break;
@@ -850,7 +885,12 @@ static lbm_status run_diagnostics(lbm_handle* h, int32_t k, const double* d_ref,
     }
 #undef E
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(256), 0, h->stream, partials, nblocks, res_dev);
+        hipLaunchKernelGGL(k_diag_reduce, dim3(dl.groups), dim3(256), 0, h->stream, partials, dl.tiles, dl.chunk,
+                           groups);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(256), 0, h->stream, groups, dl.groups, dl.groups, res_dev);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(res, res_dev, sizeof res, hipMemcpyDeviceToHost, h->stream);
@@ -894,7 +934,7 @@ extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_
             return fail(LBM_EDEVICE, "u_ref upload failed: %s", hipGetErrorString(e));
         }
     }
-    st = run_diagnostics(h, k, d_ref, h->d_partials, h->d_out, out);
+    st = run_diagnostics(h, k, d_ref, h->d_partials, out);
     dev_free(h, d_ref);
     return st;
 }
@@ -1058,6 +1098,27 @@ extern "C" lbm_status lbm_decode(int32_t storage, const uint16_t* d_in, float* d
     if (n == 0) return LBM_OK;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, storage, d_in, d_out, n);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_memory_probe(int32_t kind, const void* d_src, void* d_dst, size_t bytes, void* stream) {
+    if (kind == LBM_PROBE_COPY) return lbm_copy_probe(d_src, d_dst, bytes, stream);
+    if (kind < LBM_PROBE_READ || kind > LBM_PROBE_WRITE_MISALIGNED) return fail(LBM_EINVAL, "unknown probe kind %d", kind);
+    const bool read = kind == LBM_PROBE_READ || kind == LBM_PROBE_READ_MISALIGNED;
+    const uint32_t shift = (kind == LBM_PROBE_READ_MISALIGNED || kind == LBM_PROBE_WRITE_MISALIGNED) ? 1u : 0u;
+    if ((read && !d_src) || !d_dst || (bytes % 4) || ((uintptr_t)d_src % 4) || ((uintptr_t)d_dst % 4) || bytes < 8)
+        return fail(LBM_EINVAL, "memory probe needs 4-byte aligned pointers and a size of at least 8, a multiple of 4");
+    const size_t n = bytes / 4 - shift;            // elements accessed, shift .. shift + n - 1
+    const size_t threads = 256;
+    const size_t blocks = std::min<size_t>((n + threads - 1) / threads, (size_t)1 << 20);
+    if (read) {
+        hipLaunchKernelGGL(k_mem_read, dim3((unsigned)blocks), dim3(threads), 0, (hipStream_t)stream,
+                           (const uint32_t*)d_src, (uint32_t*)d_dst, n, shift);
+    } else {
+        hipLaunchKernelGGL(k_mem_write, dim3((unsigned)blocks), dim3(threads), 0, (hipStream_t)stream, (uint32_t*)d_dst,
+                           n, shift);
+    }
     HIP_TRY(hipGetLastError());
     return LBM_OK;
 }

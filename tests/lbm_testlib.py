@@ -4,11 +4,27 @@ lattices from the same seeded inputs, and comparing their states.
 Tolerances (derived from the arithmetic):
   FP64 storage + FP64 arithmetic: relative 1e-12 after many steps (the two
     sides differ only in FMA contraction and summation rounding, ~1e-16 per op);
-  FP32 arithmetic: one step differs from the FP64 reference by the FP32
-    rounding of terms of size <= ~0.5, i.e. a few 1e-8 absolute; we allow
-    ARITH32_ABS = 5e-7;
-  16-bit storage: the GPU code must decode to within half a code spacing
-    (the storage rounding) plus ARITH32_ABS of the reference's exact value.
+  FP32 arithmetic, one step: a stored value f'_i = f_i - omega (f_i - feq_i)
+    (+ the Guo source) carries the rounding of the final operations, a few
+    eps |f_i| and eps |f'_i|, and the rounding of the density and velocity
+    it is computed from: the density is a sum of the q pulled DDFs plus 1
+    (error ~ eps (1 + sum |f_j|)), the velocity j / rho likewise, and feq_i
+    depends on both with weight ~ w_i, scaled by the relaxation rate.  So
+        E_i = K eps (omega_max w_i (1 + S) + |f'_i| + M),
+    eps = 2^-24, S = q max |f_in| bounds the sum of the pulled |f_j|, M =
+    max |f_in|; K = 4 for SRT and TRT (a float32 emulation of the SRT step
+    stays below 1.6 eps omega w_i (1 + S)), 16 for MRT, whose moment
+    transforms sum 19 terms with integer coefficients up to 24;
+  the GPU's float result is within E_i of the exact value and its code the
+    nearest to that float, the reference's code the nearest to the exact
+    value, so |decoded GPU - reference| <= half spacing at the GPU code +
+    half spacing at the reference code + E_i (float32: half an ulp each);
+  16-bit formats: at least 99.8 % of the codes are identical on the
+    near-equilibrium one-step states (the measured floor, 99.84 % for FP16C,
+    is set by the values whose exact result lies within E_i of a rounding
+    boundary between two codes: near zero the codes of FP16C and FP16S are
+    closer together than E_i), at least 98 % on the white-noise full-size
+    states (measured floor 98.6 %), which put more values near zero.
 """
 from __future__ import annotations
 
@@ -18,7 +34,30 @@ import numpy as np
 
 import lbm_workloads as wl
 
-ARITH32_ABS = 5e-7
+EPS32 = 2.0 ** -24
+MIN_SAME_16BIT = 0.998
+# The full-size sampled states are white noise around rest (each DDF one of
+# 4096 values w_i a, a uniform in +-0.05), so about 1 % of the values lie
+# closer to zero than where FP16C and FP16S codes are E_i apart; measured
+# floor 98.6 % (an ensemble lattice in FP16S), 98.7 % for the FP16C cavity.
+MIN_SAME_SYNTHETIC = 0.98
+
+
+class StepBar:
+    """E_i of the one-step FP32 comparison (see the module docstring) for
+    velocity set q, relaxation time tau, collision and the pre-step DDFs."""
+
+    def __init__(self, orc, q, tau, collision, f_in, trt_magic=0.25):
+        _, w, _ = orc.velset(q)
+        wp, wm = orc.relaxation_rates(tau, trt_magic)
+        om = max(wp, wm) if collision == "trt" else (max(wp, 1.98) if collision == "mrt" else wp)
+        M = float(np.abs(np.asarray(f_in, dtype=np.float64)).max()) if np.size(f_in) else 0.0
+        K = 16.0 if collision == "mrt" else 4.0
+        self.base = K * EPS32 * (om * w * (1.0 + q * M) + M)       # per direction i
+        self.K = K
+
+    def bound(self, ref_f):
+        return self.base[:, None] + self.K * EPS32 * np.abs(ref_f)
 
 
 def say(*args):
@@ -63,26 +102,40 @@ def half_spacing(orc, storage: str, values: np.ndarray) -> np.ndarray:
     return 0.5 * np.maximum(np.abs(up - here), np.abs(here - down))
 
 
-def assert_step_parity(orc, storage: str, gpu_codes: np.ndarray, ref_f: np.ndarray, label: str = ""):
+def half_ulp32(values: np.ndarray) -> np.ndarray:
+    v = np.abs(values.astype(np.float32))
+    return 0.5 * (np.nextafter(v, np.float32(np.inf)).astype(np.float64) - v.astype(np.float64))
+
+
+def assert_step_parity(orc, storage: str, gpu_codes: np.ndarray, ref_f: np.ndarray, label: str = "",
+                       bar: StepBar | None = None, min_same: float | None = None):
     """One-step comparison of GPU stored codes with reference FP64 values
-    computed from the same inputs (reference stored through the format)."""
+    computed from the same inputs (reference stored through the format).
+    bar: the FP32 arithmetic bound (required for FP32 arithmetic); min_same:
+    least fraction of identical codes (default MIN_SAME_16BIT for 16-bit
+    formats).  Returns the fraction of identical codes."""
     if storage == "fp64":
         scale = np.abs(ref_f).max()
         err = np.abs(gpu_codes - ref_f).max()
         assert err <= 1e-13 * scale, (label, err, scale)
         return 1.0
+    assert bar is not None, "FP32 arithmetic needs a StepBar"
+    E = bar.bound(ref_f)
     if storage == "fp32":
-        err = np.abs(gpu_codes.astype(np.float64) - ref_f).max()
-        assert err <= ARITH32_ABS, (label, err)
-        return float(np.mean(gpu_codes == ref_f.astype(np.float32)))
-    got = orc.decode(storage, gpu_codes)
-    # |got - ref| <= (GPU rounding: half spacing at got) + (reference rounding:
-    # half spacing at ref) + (FP32 arithmetic error before the rounding)
-    bound = half_spacing(orc, storage, got) + half_spacing(orc, storage, ref_f) + ARITH32_ABS
+        got = gpu_codes.astype(np.float64)
+        bound = half_ulp32(got) + half_ulp32(ref_f) + E
+        same = float(np.mean(gpu_codes == ref_f.astype(np.float32)))
+    else:
+        got = orc.decode(storage, gpu_codes)
+        bound = half_spacing(orc, storage, got) + half_spacing(orc, storage, ref_f) + E
+        same = float(np.mean(gpu_codes == ref_codes(orc, storage, ref_f)))
     err = np.abs(got - ref_f)
     bad = err > bound * (1 + 1e-12)
-    assert not bad.any(), (label, int(bad.sum()), float(err[bad].max()) if bad.any() else 0.0)
-    same = float(np.mean(gpu_codes == ref_codes(orc, storage, ref_f)))
+    assert not bad.any(), (label, int(bad.sum()), float(err[bad].max()) if bad.any() else 0.0,
+                           float(bound[bad].min()) if bad.any() else 0.0)
+    if storage != "fp32":
+        floor = MIN_SAME_16BIT if min_same is None else min_same
+        assert same >= floor, (label, "identical codes", same)
     return same
 
 
@@ -137,7 +190,7 @@ def sample_points(dims, rng, n_random=1200, extra=None):
 
 
 def check_samples(orc, storage, q, collision, tau, dims, flags, codes_in, codes_out, pts, label,
-                  force=(0.0, 0.0, 0.0), wall_u=(0.0, 0.0, 0.0)):
+                  force=(0.0, 0.0, 0.0), wall_u=(0.0, 0.0, 0.0), min_same=MIN_SAME_SYNTHETIC):
     """Reference step of each sampled cell from its 3x3x3 neighbourhood;
     returns the fraction of identical codes and the number of compared
     non-wall cells.  Wall cells must keep their codes exactly; EQ cells are
@@ -157,12 +210,13 @@ def check_samples(orc, storage, q, collision, tau, dims, flags, codes_in, codes_
     ref = orc.Lattice(3 * S, 3, 3, q=q, tau=tau, collision=collision, storage=storage, force=force,
                       wall_u=wall_u, flags=fl3)
     ref.f = decode_codes(orc, storage, codes_in[:, big])
+    bar = StepBar(orc, q, tau, collision, ref.f)
     ref.step(1)
     exp = ref.f[:, centre_small]
     got = codes_out[:, centre_big]
     solid = (flags[centre_big] & wl.SOLID) != 0
     assert np.array_equal(got[:, solid], codes_in[:, centre_big][:, solid]), label
-    same = assert_step_parity(orc, storage, got[:, ~solid], exp[:, ~solid], label)
+    same = assert_step_parity(orc, storage, got[:, ~solid], exp[:, ~solid], label, bar=bar, min_same=min_same)
     return same, int((~solid).sum())
 
 

@@ -80,6 +80,12 @@ def test_codec_entry_points_reject_bad_arguments_without_device():
         lbm.lbm_decode("fp16c", 16, 16, -1)
     with pytest.raises(lbm.LbmError):
         lbm.lbm_copy_probe(16, 32, 17)
+    for kind, src, dst, n in [(7, 16, 32, 64), (-1, 16, 32, 64), ("read", 16, 32, 18), ("read", 18, 32, 64),
+                              ("write", 16, 34, 64), ("write_misaligned", 0, 0, 64), ("read", 0, 32, 64),
+                              ("read_misaligned", 16, 32, 4)]:
+        with pytest.raises(lbm.LbmError) as ei:
+            lbm.lbm_memory_probe(kind, src, dst, n)
+        assert ei.value.code == -1, (kind, src, dst, n)
     # n == 0 is a no-op and touches no device
     lbm.lbm_encode("fp16c", 0, 0, 0)
     assert np.dtype(np.uint16).itemsize == 2

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import lbm_workloads as wl
-from lbm_testlib import assert_step_parity, ref_codes, say
+from lbm_testlib import StepBar, assert_step_parity, ref_codes, say
 
 pytestmark = pytest.mark.gpu
 
@@ -77,7 +77,8 @@ def test_largest_lattice_one_step(lbm, orc, storage, dims):
             moved = np.abs(exp[:, lid_layer & (pts[:, 0] > 0) & (pts[:, 0] < nx - 1)
                                & (pts[:, 1] > 0) & (pts[:, 1] < ny - 1)]).max()
             assert moved > 1e-3                           # the lid has moved something
-            assert_step_parity(orc, storage, got, exp, f"{storage} {cfg}")
+            assert_step_parity(orc, storage, got, exp, f"{storage} {cfg}",
+                               bar=StepBar(orc, 19, 0.6, "trt", np.zeros((19, 1))))
             same = float(np.mean(got == ref_codes(orc, storage, exp)))
             say(f"  {cfg}: {len(n_big)} sampled cells, identical codes {same:.4f}")
             del got

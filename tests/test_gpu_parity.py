@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import lbm_workloads as wl
-from lbm_testlib import assert_step_parity, decode_codes, one_step_inputs, ref_codes, say
+from lbm_testlib import StepBar, assert_step_parity, decode_codes, one_step_inputs, ref_codes, say
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +66,7 @@ def test_one_step_from_identical_codes(lbm, orc, storage, q, collision):
     noise = wl.random_noise(q, ref.N, seed=3) * (flags == 0)
     ref.f = orc.store(storage, ref.f + noise)
     codes = ref_codes(orc, storage, ref.f)
+    bar = StepBar(orc, q, 0.56, collision, ref.f)
 
     p = lbm.make_params(nx, ny, nz, q=q, collision=collision, storage=storage, arith=_arith(storage),
                         tau=0.56, force=force, wall_u=wall_u, eq_rho=1.02, eq_u=eq_u)
@@ -75,7 +76,7 @@ def test_one_step_from_identical_codes(lbm, orc, storage, q, collision):
         g.step(1)
         out = g.get_ddf(0)
     ref.step(1)
-    same = assert_step_parity(orc, storage, out, ref.f, f"{storage} Q{q} {collision}")
+    same = assert_step_parity(orc, storage, out, ref.f, f"{storage} Q{q} {collision}", bar=bar)
     say("  identical codes:", same)
 
 
@@ -107,9 +108,16 @@ def test_fp64_taylor_green_matches_reference(lbm, orc):
 
 def test_fp32_taylor_green_within_tolerance(lbm, orc):
     """Same vortex, FP32 storage and arithmetic: relative L2 of u against the
-    FP64 reference after 1000 steps.  The bar is 4e-5: the paper's operation
-    order carried out in FP32 (numpy float32 emulation of this exact case)
-    ends 2.0e-5 away from FP64, so FP32 arithmetic itself sets the floor."""
+    FP64 reference after 1000 steps.  FP32 arithmetic with FP32 storage has a
+    floor here: the float32 emulation of the listing's operation order
+    (tests/fp32_emulation.py, pinned by tests/test_fp32_floor.py) ends
+    2.0e-5 from FP64, above the 1e-5 stated for FP32/FP32, because every
+    stored DDF is rounded to float32 each step.  So the GPU must (a) follow
+    that emulation (relative L2 between them <= 1e-6: the same operations
+    in the same order, up to the emulation's double rounding of FMAs) and
+    (b) end no further from FP64 than 1.1 times the emulation's floor."""
+    from test_fp32_floor import fp32_floor
+    from fp32_emulation import srt_run
     n, tau, u0, steps = 32, 0.6, 0.05, 1000
     rho, u = wl.taylor_green_fields(n, n, n, u0)
     ref = orc.Lattice(n, n, n, q=19, tau=tau).init(rho, u)
@@ -120,9 +128,79 @@ def test_fp32_taylor_green_within_tolerance(lbm, orc):
         g.set_rho_u(0, rho, u)
         g.step(steps)
         _, u_g = g.get_rho_u(0)
-    err = np.linalg.norm(u_g - u_r) / np.linalg.norm(u_r)
-    say("fp32 tgv rel L2", err)
-    assert err <= 4e-5
+    c, w, _ = orc.velset(19)
+    u_e = srt_run(c.tolist(), w, rho, u, (n, n, n), tau, steps)
+    floor = float(np.linalg.norm(u_e - u_r) / np.linalg.norm(u_r))
+    err = float(np.linalg.norm(u_g - u_r) / np.linalg.norm(u_r))
+    dev = float(np.linalg.norm(u_g - u_e) / np.linalg.norm(u_r))
+    say("fp32 tgv rel L2 vs FP64", err, "emulated floor", floor, "GPU vs emulation", dev)
+    assert dev <= 1e-6
+    assert err <= 1.1 * floor
+
+
+def test_fp64_arith_fp32_storage_one_step(lbm, orc):
+    """The paper's FP64/FP32 column (FP64 arithmetic, DDFs stored as FP32;
+    Table 5): one GPU step from identical float32 DDFs against the
+    reference with FP32 storage emulated (FP64 arithmetic, every stored
+    value rounded to float32).  Both sides round an FP64 result to float32,
+    so the stored values agree exactly except where the two FP64 results
+    (which differ by FMA placement, ~1e-16 relative) straddle a float32
+    rounding boundary: >= 99.99 % identical, the rest one float32 ulp
+    apart."""
+    nx, ny, nz, q = 300, 6, 5, 19
+    flags, rho, u = one_step_inputs(nx, ny, nz, q, seed=83)
+    force, wall_u, eq_u = (1e-4, -2e-5, 3e-5), (0.0, 0.08, 0.01), (0.05, 0.0, 0.0)
+    for collision in ("srt", "trt", "mrt"):
+        ref = orc.Lattice(nx, ny, nz, q=q, tau=0.56, collision=collision, storage="fp32", force=force,
+                          wall_u=wall_u, flags=flags)
+        eq = (flags & wl.EQ) != 0
+        rho0, u0 = rho.copy(), u.copy()
+        rho0[eq] = 1.02
+        u0[:, eq] = np.array(eq_u)[:, None]
+        ref.init(rho0, u0)
+        ref.f = orc.store("fp32", ref.f + wl.random_noise(q, ref.N, seed=13) * (flags == 0))
+        codes = ref.f.astype(np.float32)
+        p = lbm.make_params(nx, ny, nz, q=q, collision=collision, storage="fp32", arith="fp64", tau=0.56,
+                            force=force, wall_u=wall_u, eq_rho=1.02, eq_u=eq_u)
+        with lbm.Lattices(p) as g:
+            g.set_boundaries(0, flags)
+            g.set_ddf(0, codes)
+            g.step(1)
+            out = g.get_ddf(0)
+        ref.step(1)
+        exp = ref.f.astype(np.float32)
+        same = float(np.mean(out == exp))
+        ulps = np.abs(out.view(np.int32).astype(np.int64) - exp.view(np.int32).astype(np.int64))
+        say("fp64/fp32 one step", collision, "identical", same, "max ulps", int(ulps.max()))
+        assert same >= 0.9999, collision
+        assert ulps.max() <= 1, collision
+
+
+def test_fp64_arith_fp32_storage_taylor_green(lbm, orc):
+    """FP64/FP32 Taylor-Green vortex (D3Q19 SRT, 32^3, tau 0.6, u0 0.05, 1000
+    steps) against the reference with FP32 storage emulated: the two runs
+    round the same FP64 values to float32, so they stay within 1e-7
+    (relative L2 of u); against FP64 storage the FP32 storage rounding
+    shows, as in the paper's FP64/FP32 column, at the level of the FP32
+    floor (below 2.5e-5)."""
+    n, tau, u0, steps = 32, 0.6, 0.05, 1000
+    rho, u = wl.taylor_green_fields(n, n, n, u0)
+    ref = orc.Lattice(n, n, n, q=19, tau=tau, storage="fp32").init(rho, u)
+    ref.step(steps)
+    _, u_r = ref.moments()
+    ref64 = orc.Lattice(n, n, n, q=19, tau=tau).init(rho, u)
+    ref64.step(steps)
+    _, u_64 = ref64.moments()
+    p = lbm.make_params(n, n, n, q=19, storage="fp32", arith="fp64", tau=tau)
+    with lbm.Lattices(p) as g:
+        g.set_rho_u(0, rho, u)
+        g.step(steps)
+        _, u_g = g.get_rho_u(0)
+    err = float(np.linalg.norm(u_g - u_r) / np.linalg.norm(u_r))
+    err64 = float(np.linalg.norm(u_g - u_64) / np.linalg.norm(u_64))
+    say("fp64/fp32 tgv vs emulated-storage reference", err, "vs FP64", err64)
+    assert err <= 1e-7
+    assert err64 <= 2.5e-5
 
 
 def test_batched_equals_per_lattice_and_graph(lbm, orc):
@@ -230,7 +308,7 @@ def test_nonfinite_detected(lbm):
         f = g.get_ddf(0)
         f[3, 100] = np.nan
         g.set_ddf(0, f)
-        d = lbm.lbm_diagnostics(g.h, 0)
+        d = lbm.lbm_diagnostics(g.h, 0, g.N(0))
         assert d.nonfinite_cells >= 1
 
 
@@ -444,6 +522,7 @@ def test_unshifted_one_step(lbm, orc, storage):
     ref = orc.Lattice(nx, ny, nz, q=q, tau=0.6, collision=collision, storage=storage, shifted=False,
                       wall_u=(0.0, 0.05, 0.0), flags=flags).init(rho, u)
     codes = ref_codes(orc, storage, ref.f)
+    bar = StepBar(orc, q, 0.6, collision, ref.f)
     p = lbm.make_params(nx, ny, nz, q=q, collision=collision, storage=storage, tau=0.6,
                         wall_u=(0.0, 0.05, 0.0), unshifted=True)
     with lbm.Lattices(p) as g:
@@ -452,7 +531,7 @@ def test_unshifted_one_step(lbm, orc, storage):
         g.step(1)
         out = g.get_ddf(0)
     ref.step(1)
-    same = assert_step_parity(orc, storage, out, ref.f, f"unshifted {storage}")
+    same = assert_step_parity(orc, storage, out, ref.f, f"unshifted {storage}", bar=bar)
     say("  identical codes:", same)
 
 
@@ -535,13 +614,14 @@ def test_one_step_other_velocity_sets(lbm, orc, storage, q, collision):
     noise = wl.random_noise(q, ref.N, seed=5) * (flags == 0)
     ref.f = orc.store(storage, ref.f + noise)
     codes = ref_codes(orc, storage, ref.f)
+    bar = StepBar(orc, q, 0.56, collision, ref.f)
     p = lbm.make_params(nx, ny, nz, q=q, collision=collision, storage=storage, arith=_arith(storage),
                         tau=0.56, force=force, wall_u=wall_u, eq_rho=1.02, eq_u=eq_u)
     out = _one_gpu_step(lbm, p, flags, codes)
     out_dense = _one_gpu_step(lbm, p, flags, codes, dict(mode=2, block=128))   # cell-contiguous tiles
     ref.step(1)
     assert np.array_equal(out, out_dense)
-    same = assert_step_parity(orc, storage, out, ref.f, f"{storage} Q{q} {collision}")
+    same = assert_step_parity(orc, storage, out, ref.f, f"{storage} Q{q} {collision}", bar=bar)
     say("  identical codes:", same)
 
 
@@ -591,13 +671,14 @@ def test_one_step_mrt(lbm, orc, storage):
     noise = wl.random_noise(19, ref.N, seed=7) * (flags == 0)
     ref.f = orc.store(storage, ref.f + noise)
     codes = ref_codes(orc, storage, ref.f)
+    bar = StepBar(orc, 19, 0.56, "mrt", ref.f)
     p = lbm.make_params(nx, ny, nz, q=19, collision="mrt", storage=storage, arith=_arith(storage),
                         tau=0.56, force=force, wall_u=wall_u, eq_rho=1.02, eq_u=eq_u)
     out = _one_gpu_step(lbm, p, flags, codes)
     out_dense = _one_gpu_step(lbm, p, flags, codes, dict(mode=2, block=256))
     ref.step(1)
     assert np.array_equal(out, out_dense)
-    same = assert_step_parity(orc, storage, out, ref.f, f"{storage} MRT")
+    same = assert_step_parity(orc, storage, out, ref.f, f"{storage} MRT", bar=bar)
     say("  identical codes:", same)
 
 
