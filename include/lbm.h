@@ -232,6 +232,23 @@ lbm_status lbm_get_ddf(lbm_handle* h, int32_t lattice, void* host);
  * u_ref), LBM_EDEVICE. */
 lbm_status lbm_diagnostics(lbm_handle* h, int32_t lattice, const double* u_ref, lbm_diag* out);
 
+/* For callers that cannot allocate device memory (code around a HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * diagnostics of lbm_diagnostics without any allocation.  u_ref_dev: NULL
+ * or a DEVICE array of 3*N doubles laid out as lbm_diagnostics' u_ref (owned
+ * by the caller).  The reduction's partial sums and results go to a static
+ * device array of the library (32 MiB per GPU, held until the process ends)
+ * instead of memory of the handle: 12 doubles per row tile of up to 512
+ * cells (ny * nz * ceil(nx / 512) tiles) plus 513 * 12 doubles, so lattices
+ * of up to about 349,000 row tiles (a 512^3 lattice has 262,144); a larger
+ * lattice is refused with LBM_EINVAL and a message giving both sizes.
+ * Every call on one GPU shares the array and leaves its contents there, so
+ * calls that overlap on one GPU (from other threads, or on other streams)
+ * race and must be serialised by the caller.  Results are bit-identical to
+ * lbm_diagnostics with the same reference field.  Synchronises.  Errors:
+ * as lbm_diagnostics (LBM_ENONFINITE after filling *out). */
+lbm_status lbm_diagnostics_noalloc(lbm_handle* h, int32_t lattice, const double* u_ref_dev, lbm_diag* out);
+
 /* Launch configuration (see lbm_launch); invalid values are LBM_EINVAL and
  * leave the current configuration in place.  Setting one drops a captured
  * graph (it is captured again at the next lbm_step).  If the batched tile

@@ -106,6 +106,7 @@ def library():
         "lbm_set_ddf": (S, [_P, ctypes.c_int32, _P]),
         "lbm_get_ddf": (S, [_P, ctypes.c_int32, _P]),
         "lbm_diagnostics": (S, [_P, ctypes.c_int32, _P, ctypes.POINTER(LbmDiag)]),
+        "lbm_diagnostics_noalloc": (S, [_P, ctypes.c_int32, _P, ctypes.POINTER(LbmDiag)]),
         "lbm_set_launch": (S, [_P, ctypes.POINTER(LbmLaunch)]),
         "lbm_get_launch": (S, [_P, ctypes.POINTER(LbmLaunch)]),
         "lbm_autotune": (S, [_P, ctypes.c_int32, ctypes.POINTER(LbmLaunch)]),
@@ -264,6 +265,17 @@ def lbm_diagnostics(h, lattice: int, N: int, u_ref: np.ndarray | None = None) ->
     d = LbmDiag()
     ref = None if u_ref is None else _check_host(u_ref, 3 * N, np.float64, "u_ref")
     rc = library().lbm_diagnostics(h, lattice, _host_ptr(ref), ctypes.byref(d))
+    if rc not in (0, -5):
+        _check(rc)
+    return d
+
+
+def lbm_diagnostics_noalloc(h, lattice: int, u_ref_dev: int | None = None) -> LbmDiag:
+    """lbm_diagnostics without allocation; u_ref_dev: None or the device
+    address of 3*N doubles (e.g. a torch tensor's data_ptr()).  Raises like
+    lbm_diagnostics."""
+    d = LbmDiag()
+    rc = library().lbm_diagnostics_noalloc(h, lattice, u_ref_dev, ctypes.byref(d))
     if rc not in (0, -5):
         _check(rc)
     return d

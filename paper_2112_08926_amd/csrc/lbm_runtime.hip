@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -281,6 +282,41 @@ __global__ void __launch_bounds__(256) k_mem_write(uint32_t* __restrict__ dst, s
         dst[i + shift] = (uint32_t)i;
 }
 
+// ------------------------------------------------------------------ static scratch
+// Device memory of lbm_diagnostics_noalloc: the reduction's partials (one set
+// of kDiagFields doubles per row tile of the first pass, then per workgroup of
+// the second, then the results), in a file-scope device array instead of
+// memory of the handle, so that the entry point allocates nothing.  32 MiB:
+// lattices of up to 349,000 row tiles (a 512^3 lattice has 262,144).  Each GPU
+// holds its own copy for the life of the process.  In host code the array's
+// name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device, kept per device below.
+constexpr size_t kScratchDoubles = (size_t)4 << 20;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices];
+
+// Address of the current device's scratch array, looked up once per device
+// (at handle creation, with that device current).
+static lbm_status scratch_address(double** out) {
+    *out = nullptr;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBM_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
 // ------------------------------------------------------------------ handle
 struct Lattice {
     lbm_params p{};
@@ -335,6 +371,8 @@ struct lbm_handle {
     unsigned long long* d_nonfinite = nullptr;
     // size of every device allocation the handle holds (for device_bytes)
     std::unordered_map<void*, size_t> sizes;
+    // this device's static scratch array (lbm_diagnostics_noalloc)
+    double* scratch = nullptr;
 };
 
 // Reduction layout of lattice L: `tiles` first-pass partials (one per row
@@ -493,6 +531,11 @@ extern "C" lbm_status lbm_create(const lbm_params* params, int32_t n_lattices, v
         return fail(LBM_EDEVICE, "no HIP device");
     }
     h->num_cus = prop.multiProcessorCount;
+    lbm_status sst = scratch_address(&h->scratch);
+    if (sst != LBM_OK) {
+        delete h;
+        return sst;
+    }
     h->launch = {n_lattices > 1 ? LBM_LAUNCH_BATCHED : LBM_LAUNCH_PER_LATTICE, 256, 1, 0, 0};
     lbm_status st = device_table(h->storage, &h->enc);
     if (st != LBM_OK) { delete h; return st; }
@@ -937,6 +980,19 @@ extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_
     st = run_diagnostics(h, k, d_ref, h->d_partials, out);
     dev_free(h, d_ref);
     return st;
+}
+
+extern "C" lbm_status lbm_diagnostics_noalloc(lbm_handle* h, int32_t k, const double* u_ref_dev, lbm_diag* out) {
+    lbm_status st = check_lattice(h, k);
+    if (st != LBM_OK) return st;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    const size_t need = diag_doubles(diag_layout(h->lats[k]));
+    if (need > kScratchDoubles)
+        return fail(LBM_EINVAL, "lattice %d needs %zu bytes of reduction scratch; the static array holds %zu "
+                    "(lbm_diagnostics has no such limit)", k, need * sizeof(double), kScratchDoubles * sizeof(double));
+    // every first-pass workgroup writes all of its slot and each later pass
+    // writes every slot the next one reads, so nothing needs clearing
+    return run_diagnostics(h, k, u_ref_dev, h->scratch, out);
 }
 
 // ------------------------------------------------------------------ launch configuration
