@@ -1,18 +1,23 @@
 // lbm_codecs.h -- conversion between FP32 (or FP64) arithmetic values and the
 // DDF storage formats of Sec. 3 / Table 2 of the paper, for gfx950.
 //
-// Decoders are branch-free bit manipulation (one leading-zero count for the
-// posits).  FP16 and FP16S use the hardware f32<->f16 conversions (round to
-// nearest even).  FP16C encodes arithmetically (fp16c_encode).  The posits
-// encode through a 256-entry table
-// indexed by the FP32 exponent field: inside one FP32 binade the codes of
-// these formats are either evenly spaced (code = first code + rounded
-// mantissa, the carry running into the next binade) or absent (one threshold
-// between the two neighbouring codes), so
-//     code = base[E] + min((mantissa + bias[E]) >> shift[E], cap[E])
+// Decoders are branch-free bit manipulation (one leading-bit count for the
+// posits), written on the sign-extended 16-bit code that a sign-extending
+// load gives, so that the sign is already at bit 31.  FP16 and FP16S use the
+// hardware f32<->f16 conversions (round to nearest even).  FP16C encodes
+// arithmetically (fp16c_encode).  The posits encode through a small table:
+// inside one FP32 binade E the codes of these formats are either evenly
+// spaced (code = first code + rounded mantissa, the carry running into the
+// next binade) or absent (one threshold between the two neighbouring codes),
+// so
+//     code = sign | base[E] + min((mantissa + bias[E]) >> shift[E], cap[E])
 // rounds every float to the nearest code with ties away from zero, and
-// saturates above the largest code.  The table is built on the host from
-// the decoders below (build_encoder_table in the runtime).
+// saturates above the largest code.  All binades below a format's window
+// round to the same code (zero), all above it to the largest code, so the
+// table holds only the window's 64 binades per sign, the exponent clamped
+// into it; base carries the sign and bias cancels the sign and exponent bits,
+// so the mantissa need not be masked out (see table_encode).  It is built on
+// the host from the decoders below (lbm_enc_table.h).
 //
 // Every function here is __host__ __device__ so that the host can build the
 // tables from exactly the device decoders.
@@ -65,36 +70,105 @@ __host__ __device__ __forceinline__ uint16_t fp16c_encode(float x) {
 
 // ---------------------------------------------------------------- posits
 // Sign-magnitude posits (Sec. 3.2.3): the 15 magnitude bits are placed at the
-// top of a 32-bit word; the regime is the run of equal leading bits.
-// P16_0S / P16_1S additionally carry the range shift x*2^7, undone here by
-// the exponent bias 127 - 7.
+// top of a 32-bit word t; the regime is the run of equal leading bits, k long,
+// with r = k - 1 for a run of ones and -k for zeros; the terminating bit is
+// skipped, ES exponent bits and the fraction follow.  P16_0S / P16_1S
+// additionally carry the range shift x*2^7, undone here by the exponent bias
+// 127 - 7.  cs: the code sign-extended to 32 bits.
+//
+// On the device each decoder is one fixed instruction sequence: the run
+// length is one v_ffbh_i32 (leading bits equal to bit 31; -1 for t = 0, whose
+// result the zero select discards), r + 120 one v_xad_u32 ((-k ^ s) + 120),
+// the fraction one v_bfe_u32.  The zero test is issued early, so that the
+// select that reads its mask comes well after the compare that writes it.
 template <int ES>
-__host__ __device__ __forceinline__ float posit_s_decode(uint32_t c) {
-    const uint32_t mag = c & 0x7FFFu;
-    const uint32_t t = mag << 17;
-    const uint32_t s = (uint32_t)((int32_t)t >> 31);     // all ones for a regime of ones (r >= 0)
-    const int k = __builtin_clz((t ^ s) | 1u);           // run length (mag != 0)
-    const int r = (k - 1) ^ (int)~s;                     // k - 1 for ones, -k for zeros
+__host__ __device__ __forceinline__ float posit_s_decode_sext(int32_t cs) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t out, t, k, s, r, sh;
+    if constexpr (ES == 0)
+        asm("v_lshlrev_b32 %1, 17, %6\n\t"
+            "v_cmp_ne_u32 vcc, 0, %1\n\t"
+            "v_ffbh_i32 %2, %1\n\t"
+            "v_ashrrev_i32 %3, 31, %1\n\t"
+            "v_sub_u32 %4, 0, %2\n\t"
+            "v_xad_u32 %4, %4, %3, %8\n\t"
+            "v_lshlrev_b32 %5, %2, %1\n\t"
+            "v_bfe_u32 %5, %5, 8, 23\n\t"
+            "v_lshl_or_b32 %4, %4, 23, %5\n\t"
+            "v_cndmask_b32 %4, 0, %4, vcc\n\t"
+            "v_and_or_b32 %0, %6, %7, %4"
+            : "=v"(out), "=&v"(t), "=&v"(k), "=&v"(s), "=&v"(r), "=&v"(sh)
+            : "v"(cs), "s"(0x80000000u), "s"(120u)
+            : "vcc");
+    else                                                  // exponent bit on bit 23: r + 120 at 24, 120 = 2 * 60
+        asm("v_lshlrev_b32 %1, 17, %6\n\t"
+            "v_cmp_ne_u32 vcc, 0, %1\n\t"
+            "v_ffbh_i32 %2, %1\n\t"
+            "v_ashrrev_i32 %3, 31, %1\n\t"
+            "v_sub_u32 %4, 0, %2\n\t"
+            "v_xad_u32 %4, %4, %3, %8\n\t"
+            "v_lshlrev_b32 %5, %2, %1\n\t"
+            "v_bfe_u32 %5, %5, 7, 24\n\t"
+            "v_lshl_or_b32 %4, %4, 24, %5\n\t"
+            "v_cndmask_b32 %4, 0, %4, vcc\n\t"
+            "v_and_or_b32 %0, %6, %7, %4"
+            : "=v"(out), "=&v"(t), "=&v"(k), "=&v"(s), "=&v"(r), "=&v"(sh)
+            : "v"(cs), "s"(0x80000000u), "s"(60u)
+            : "vcc");
+    return u2f(out);
+#else
+    const uint32_t t = (uint32_t)cs << 17;               // magnitude at bits 31..17, sign bits dropped
+    const uint32_t s = (uint32_t)((int32_t)t >> 31);     // all ones for a run of ones
+    const int k = __builtin_clz((t ^ s) | 1u);           // run length (t != 0)
+    const int r = -k ^ (int)s;                           // k - 1 for ones, -k for zeros
     const uint32_t sh = t << k;                          // the terminator at bit 31
     uint32_t bits;
     if (ES == 0)
-        bits = ((uint32_t)r << 23) + ((sh >> 8) & 0x7FFFFFu) + (120u << 23);
+        bits = ((uint32_t)(r + 120) << 23) | ((sh >> 8) & 0x7FFFFFu);
     else
-        bits = ((uint32_t)r << 24) + ((sh >> 7) & 0xFFFFFFu) + (120u << 23);   // exponent bit on bit 23
-    bits = mag ? bits : 0u;
-    return u2f(bits | ((c & 0x8000u) << 16));
+        bits = ((uint32_t)(r + 60) << 24) | ((sh >> 7) & 0xFFFFFFu);
+    bits = t ? bits : 0u;
+    return u2f(bits | ((uint32_t)cs & 0x80000000u));
+#endif
+}
+template <int ES>
+__host__ __device__ __forceinline__ float posit_s_decode(uint32_t c) {
+    return posit_s_decode_sext<ES>((int32_t)(int16_t)(uint16_t)c);
 }
 
 // Asymmetric P16_2C: r leading zeros close with a one (no regime sign), then
 // 2 exponent bits and 12 - r mantissa bits; value 2^(-3-4r+e)(1 + m/2^(12-r)).
-__host__ __device__ __forceinline__ float p162c_decode(uint32_t c) {
-    const uint32_t mag = c & 0x7FFFu;
-    const uint32_t t = mag << 17;
+// Shifting the regime and its closing one out of the top leaves the exponent
+// bits at 31..30 and the mantissa below; the FP32 exponent field is then
+// 124 - 4r = 4 (31 - r) plus e.  Device: one fixed sequence as above (r is
+// one v_ffbh_u32).
+__host__ __device__ __forceinline__ float p162c_decode_sext(int32_t cs) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t out, t, r, rest, e;
+    asm("v_lshlrev_b32 %1, 17, %5\n\t"
+        "v_cmp_ne_u32 vcc, 0, %1\n\t"
+        "v_ffbh_u32 %2, %1\n\t"
+        "v_lshlrev_b32 %3, %2, %1\n\t"
+        "v_bfe_u32 %3, %3, 6, 25\n\t"
+        "v_sub_u32 %4, 31, %2\n\t"
+        "v_lshl_add_u32 %3, %4, 25, %3\n\t"
+        "v_cndmask_b32 %3, 0, %3, vcc\n\t"
+        "v_and_or_b32 %0, %5, %6, %3"
+        : "=v"(out), "=&v"(t), "=&v"(r), "=&v"(rest), "=&v"(e)
+        : "v"(cs), "s"(0x80000000u)
+        : "vcc");
+    return u2f(out);
+#else
+    const uint32_t t = (uint32_t)cs << 17;
     const int r = __builtin_clz(t | 1u);
-    const uint32_t rest = (t << r) << 1;                 // exponent bits at 31..30
-    uint32_t bits = (uint32_t)((124 - 4 * r) << 23) + (rest >> 7);
-    bits = mag ? bits : 0u;
-    return u2f(bits | ((c & 0x8000u) << 16));
+    const uint32_t rest = ((t << r) << 1) >> 7;          // exponent bits at 24..23, mantissa below
+    uint32_t bits = ((uint32_t)(31 - r) << 25) + rest;
+    bits = t ? bits : 0u;
+    return u2f(bits | ((uint32_t)cs & 0x80000000u));
+#endif
+}
+__host__ __device__ __forceinline__ float p162c_decode(uint32_t c) {
+    return p162c_decode_sext((int32_t)(int16_t)(uint16_t)c);
 }
 
 // ---------------------------------------------------------------- IEEE FP16
@@ -105,14 +179,56 @@ __host__ __device__ __forceinline__ uint16_t half_encode(float x) {
     return __builtin_bit_cast(uint16_t, (_Float16)x);
 }
 
-// Software encoder through the per-binade table.
-__host__ __device__ __forceinline__ uint16_t table_encode(float x, const EncEntry* tab) {
+__host__ __device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__host__ __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__host__ __device__ __forceinline__ uint32_t ubfe(uint32_t v, uint32_t off, uint32_t width) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_ubfe(v, off, width);
+#else
+    return (v >> off) & ((1u << width) - 1u);
+#endif
+}
+
+// First FP32 exponent field of a posit format's encoder window: two binades
+// below its smallest code (the lower one rounds to zero, the upper one to
+// the smallest code); the window's last binade lies above the largest code.
+__host__ __device__ constexpr uint32_t enc_window_lo(int fmt) {
+    return fmt == S_P16_0S ? 104u : fmt == S_P16_1S ? 90u : fmt == S_P16_2C ? 66u : 0u;
+}
+
+// Software encoder through the windowed per-binade table (kEncEntries
+// entries, kEncWindow per sign) of the format whose window starts at lo.
+// On the device the table is in LDS (every caller stages it there) and the
+// entry's address is one fixed sequence: the exponent field (v_bfe_u32),
+// clamped into the window (v_med3_u32), plus the sign's half (two
+// v_lshl_add_u32); then one 16-byte LDS read.
+__host__ __device__ __forceinline__ uint16_t table_encode(float x, const EncEntry* tab, uint32_t lo) {
     const uint32_t b = f2u(x);
-    const uint32_t a = b & 0x7FFFFFFFu;
-    const EncEntry e = tab[a >> 23];
-    uint32_t j = ((a & 0x7FFFFFu) + e.bias) >> e.shift;
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(3))) u32x4* LdsEntry;
+    // LDS address of the entry of exponent 0 of the positive half (the
+    // clamped exponent is added to it, scaled by the entry size)
+    const uint32_t t0 = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) EncEntry*)tab - lo * 16u;
+    uint32_t addr, e, sg;
+    asm("v_bfe_u32 %1, %3, 23, 8\n\t"
+        "v_med3_u32 %1, %1, %5, %6\n\t"
+        "v_lshrrev_b32 %2, 31, %3\n\t"
+        "v_lshl_add_u32 %0, %2, %7, %4\n\t"
+        "v_lshl_add_u32 %0, %1, 4, %0"
+        : "=&v"(addr), "=&v"(e), "=&v"(sg)
+        : "v"(b), "s"(t0), "s"(lo), "v"(lo + (kEncWindow - 1)), "i"(__builtin_ctz(kEncWindow * 16)));
+    const u32x4 ent = *(LdsEntry)(uintptr_t)addr;          // base, cap, bias, shift
+    uint32_t j = (b + ent.z) >> ent.w;
+    j = j < ent.y ? j : ent.y;
+    return (uint16_t)(ent.x + j);
+#else
+    const uint32_t E = umin(umax(ubfe(b, 23, 8), lo), lo + (kEncWindow - 1));
+    const EncEntry e = tab[((b >> 31) * kEncWindow) + (E - lo)];
+    uint32_t j = (b + e.bias) >> e.shift;
     j = j < e.cap ? j : e.cap;
-    return (uint16_t)(((b >> 16) & 0x8000u) | (e.base + j));
+    return (uint16_t)(e.base + j);
+#endif
 }
 
 // Decoded value of a 16-bit code of a format (host table builder and tests).
@@ -193,22 +309,28 @@ template <> struct Codec<S_P16_0S> : RawCodec<S_P16_0S> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
-    template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode<0>(v); }
-    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
+    template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode_sext<0>((int16_t)v); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) {
+        return table_encode(v, t, enc_window_lo(S_P16_0S));
+    }
 };
 template <> struct Codec<S_P16_1S> : RawCodec<S_P16_1S> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
-    template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode<1>(v); }
-    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
+    template <class A> __device__ __forceinline__ static A load(T v) { return posit_s_decode_sext<1>((int16_t)v); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) {
+        return table_encode(v, t, enc_window_lo(S_P16_1S));
+    }
 };
 template <> struct Codec<S_P16_2C> : RawCodec<S_P16_2C> {
     using T = uint16_t;
     static constexpr int kRawExp = 0;
     static constexpr bool kTable = true;
-    template <class A> __device__ __forceinline__ static A load(T v) { return p162c_decode(v); }
-    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) { return table_encode(v, t); }
+    template <class A> __device__ __forceinline__ static A load(T v) { return p162c_decode_sext((int16_t)v); }
+    template <class A> __device__ __forceinline__ static T store(A v, const EncEntry* t) {
+        return table_encode(v, t, enc_window_lo(S_P16_2C));
+    }
 };
 
 }  // namespace lbm

@@ -11,11 +11,20 @@
 
 namespace lbm {
 
-// For FP16C and the posits: per FP32 binade E (exponent field of |x|), the
-// parameters of code = base + min((mantissa + bias) >> shift, cap); built
-// from the decoders of lbm_codecs.h so that encode(x) is the nearest code
-// (ties away from zero), saturating at the largest magnitude code.
-inline bool build_encoder_table(int fmt, EncEntry out[256], std::string* why) {
+// For the posits: per FP32 binade E (exponent field of |x|), the parameters
+// of code = base + min((mantissa + bias) >> shift, cap); built from the
+// decoders of lbm_codecs.h so that encode(x) is the nearest code (ties away
+// from zero), saturating at the largest magnitude code.  The device table
+// keeps the binades lo .. lo + kEncWindow - 1 of the format's window (the
+// encoder clamps the exponent into it), which is only exact if every binade
+// below the window encodes like its first one and every binade above like
+// its last one, each to a single code (cap 0): checked here.  Entry s *
+// kEncWindow + (E - lo) serves sign s in binade E: its base carries the sign
+// bit (0x8000) and its bias has the 9 sign and exponent bits (s * 256 + E)
+// << 23 subtracted (mod 2^32), so that table_encode adds it to the whole FP32
+// word instead of the masked mantissa.
+inline bool build_encoder_table(int fmt, EncEntry out[kEncEntries], std::string* why) {
+    EncEntry full[256];
     const int maxc = 0x7FFF;
     std::vector<double> v(maxc + 1);
     for (int c = 0; c <= maxc; c++) v[c] = (double)decode16(fmt, (uint32_t)c);
@@ -55,8 +64,8 @@ inline bool build_encoder_table(int fmt, EncEntry out[256], std::string* why) {
                 e.base = (uint32_t)cp;
                 e.cap = 1;
                 e.shift = 23;
-                if (mid < lo) e.bias = 1u << 23;
-                else if (mid >= hi) e.bias = 0;
+                if (mid < lo) e = {(uint32_t)cf, 0, 0, 23};          // the whole binade rounds up
+                else if (mid >= hi) e = {(uint32_t)cp, 0, 0, 23};    // ... or down
                 else {
                     const double mthr = (mid / lo - 1.0) * 8388608.0;
                     if (mthr != std::floor(mthr)) { *why = "midpoint not a float"; return false; }
@@ -64,8 +73,25 @@ inline bool build_encoder_table(int fmt, EncEntry out[256], std::string* why) {
                 }
             }
         }
-        out[E] = e;
+        full[E] = e;
     }
+    const uint32_t lo = enc_window_lo(fmt), hi = lo + kEncWindow - 1;
+    if (lo == 0 || full[lo].cap != 0 || full[hi].cap != 0) {
+        *why = "window edges are not single-code binades";
+        return false;
+    }
+    for (uint32_t E = 0; E < 256; E++)
+        if ((E < lo && full[E].base != full[lo].base) || (E > hi && full[E].base != full[hi].base) ||
+            ((E < lo || E > hi) && full[E].cap != 0)) {
+            *why = "a binade outside the window encodes unlike the window's edge";
+            return false;
+        }
+    for (uint32_t sgn = 0; sgn < 2; sgn++)
+        for (uint32_t w = 0; w < (uint32_t)kEncWindow; w++) {
+            const EncEntry& e = full[lo + w];
+            const uint32_t idx = sgn * 256u + lo + w;
+            out[sgn * kEncWindow + w] = {e.base | (sgn << 15), e.cap, e.bias - (idx << 23), e.shift};
+        }
     return true;
 }
 

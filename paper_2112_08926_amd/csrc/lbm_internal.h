@@ -45,11 +45,16 @@ struct Tile {
     uint16_t lat, x0, y, z;
 };
 
-// Software encoder table of one 16-bit format, indexed by the FP32 exponent
-// field E of |x|: code = base + min((mantissa + bias) >> shift, cap).
+// Software encoder table of one posit format: for each sign and each of
+// kEncWindow FP32 binades (exponent fields lo .. lo + kEncWindow - 1 of the
+// format's window, the exponent clamped into it), code = base + min((bits(x)
+// + bias) >> shift, cap), the sign in base and the sign and exponent bits
+// cancelled by bias (see table_encode).
 struct EncEntry {
     uint32_t base, cap, bias, shift;
 };
+constexpr int kEncWindow = 64;
+constexpr int kEncEntries = 2 * kEncWindow;
 
 struct StepLaunch {
     int q, storage, arith, collision;

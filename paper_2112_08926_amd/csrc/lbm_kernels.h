@@ -612,15 +612,24 @@ __device__ __forceinline__ void eq_codes_if(const LatDev& L, bool any_eq, typena
         for (int i = 0; i < Q; i++) e[i] = eq_code<F>(L, i);
     }
 }
-// The code a cell (flags fl) stores: the collision's, or what a wall (zero)
-// or EQ cell (its equilibrium code eq) keeps.
-template <int F>
-__device__ __forceinline__ typename Codec<F>::T out_code(uint32_t fl, typename Codec<F>::T eq,
-                                                         typename Codec<F>::T code) {
+// The Q codes a cell (flags fl) stores: the collision's (c, encoded from
+// fo), or what a wall (zero) or EQ cell (the lattice's equilibrium codes)
+// keeps.  The replacement runs only in wavefronts that hold a wall or EQ
+// cell (wavefront-uniform branch), so the others store the encoded values
+// without per-direction selects.
+template <int Q, int F, class A>
+__device__ __forceinline__ void out_codes(const LatDev& L, uint32_t fl, const A (&fo)[Q], const EncEntry* tab,
+                                          typename Codec<F>::T (&c)[Q]) {
     using T = typename Codec<F>::T;
-    if (fl & F_SOLID) code = (T)0;
-    if (fl & F_EQ) code = eq;
-    return code;
+#pragma unroll
+    for (int i = 0; i < Q; i++) c[i] = Codec<F>::template store_raw<A>(fo[i], tab);
+    if (__any((fl & (F_SOLID | F_EQ)) != 0)) {
+        const bool solid = (fl & F_SOLID) != 0, eqc = (fl & F_EQ) != 0;
+        T eq[Q];
+        eq_codes_if<Q, F>(L, __any(eqc), eq);
+#pragma unroll
+        for (int i = 0; i < Q; i++) c[i] = solid ? (T)0 : (eqc ? eq[i] : c[i]);
+    }
 }
 
 // Adds the wavefront's cells whose update had a non-finite density or
@@ -634,12 +643,21 @@ __device__ __forceinline__ void count_nonfinite(const LatDev& L, bool bad) {
 }
 
 // ------------------------------------------------------------ one tile of the step
-template <int Q, int F, class A, int COLL>
+// WAVE_TABLE: `tab` is this wavefront's own LDS copy of the encoder table,
+// written by direct loads the kernel issued before calling this; the
+// wavefront waits for them (vmcnt) after its DDF loads, before the first
+// encode.  Lanes past the row's end then do not leave early (the wavefront's
+// loads must be waited for): they step the row's last cell (loads in
+// bounds) and store nothing.
+template <int Q, int F, class A, int COLL, bool WAVE_TABLE = false>
 __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t y, uint32_t z,
                                           int parity, const EncEntry* tab) {
     using T = typename Codec<F>::T;
-    const uint32_t x = x0 + threadIdx.x;
-    if (x >= L.nx) return;
+    const bool active = x0 + threadIdx.x < L.nx;
+    if constexpr (!WAVE_TABLE) {
+        if (!active) return;
+    }
+    const uint32_t x = active ? x0 + threadIdx.x : L.nx - 1;
     RowCtx rc;
     make_rows(L, y, z, rc);
     const uint32_t n = rc.rows[4] + x;
@@ -656,16 +674,16 @@ __device__ __forceinline__ void step_tile(const LatDev& L, uint32_t x0, uint32_t
     A f[Q], fo[Q];
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
     pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
+    if constexpr (WAVE_TABLE) __builtin_amdgcn_s_waitcnt(0);   // the table's direct loads have landed
     bool bad;
     collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
-    count_nonfinite(L, bad && !special);
-    T eq[Q];
-    eq_codes_if<Q, F>(L, __any((fl & F_EQ) != 0), eq);
+    count_nonfinite(L, bad && !special && active);
+    T c[Q];
+    out_codes<Q, F, A>(L, fl, fo, tab, c);
     const size_t plane = L.plane;
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < Q; i++) {
-        T* p = dst + ((size_t)i * plane + rc.rows[4]);
-        st_off(p, x, out_code<F>(fl, eq[i], Codec<F>::template store_raw<A>(fo[i], tab)));
+        for (int i = 0; i < Q; i++) st_off(dst + ((size_t)i * plane + rc.rows[4]), x, c[i]);
     }
 }
 
@@ -711,12 +729,11 @@ __device__ __forceinline__ void step_tile_dense(const LatDev& L, uint32_t x0, ui
     bool bad;
     collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);   // all lanes: fo always defined
     count_nonfinite(L, bad && !special);
-    T eq[Q];
-    eq_codes_if<Q, F>(L, __any((fl & F_EQ) != 0), eq);
+    T c[Q];
+    out_codes<Q, F, A>(L, fl, fo, tab, c);
     const size_t plane = L.plane;
 #pragma unroll
-    for (int i = 0; i < Q; i++)
-        st_off(dst + (size_t)i * plane, n, out_code<F>(fl, eq[i], Codec<F>::template store_raw<A>(fo[i], tab)));
+    for (int i = 0; i < Q; i++) st_off(dst + (size_t)i * plane, n, c[i]);
 }
 
 // ------------------------------------------------------------ several cells per lane
@@ -983,10 +1000,23 @@ __device__ __forceinline__ void step_tile_v(const LatDev& L, uint32_t x0, uint32
     for (int i = 0; i < Q; i++) vstore<T, CPL>(dst + ((size_t)i * plane + row + x), out[i]);
 }
 
+// One wavefront's copy of the encoder table, from global memory to LDS by
+// direct loads (16 bytes per lane, no registers; one instruction per 64
+// entries); the wavefront waits for them (vmcnt) before reading the table.
+static_assert(sizeof(EncEntry) == 16, "one 16-byte direct load per table entry");
+static_assert(kEncEntries % 64 == 0, "whole wavefront loads");
+__device__ __forceinline__ void fetch_wave_table(const EncEntry* g, EncEntry (&s)[kEncEntries]) {
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (uint32_t k = 0; k < (uint32_t)kEncEntries; k += 64u)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + k + lane),
+                                         (__attribute__((address_space(3))) void*)(&s[k]), 16, 0, 0);
+}
+
 template <int F>
 __device__ __forceinline__ const EncEntry* stage_table(const EncEntry* g, EncEntry* s) {
     if constexpr (Codec<F>::kTable) {
-        for (int k = threadIdx.x; k < 256; k += blockDim.x) s[k] = g[k];
+        for (int k = threadIdx.x; k < kEncEntries; k += blockDim.x) s[k] = g[k];
         __syncthreads();
         return s;
     } else {
@@ -1004,13 +1034,23 @@ __device__ __forceinline__ void run_tile(const LatDev& L, uint32_t x0, uint32_t 
 template <int Q, int F, class A, int COLL, int CPL>
 __global__ void __launch_bounds__(512) k_step_single(LatDev L, int parity, uint32_t segs,
                                                      const EncEntry* __restrict__ enc) {
-    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
-    const EncEntry* tab = stage_table<F>(enc, s_tab);
     // grid (ny, segments, nz): no index division, and the segments of one row
     // are ny workgroups apart, which for ny a multiple of 8 puts them on the
     // same XCD (workgroups go round-robin to the 8 XCDs), so the cache lines
     // their +-x neighbours share are fetched into one L2 only
-    run_tile<Q, F, A, COLL, CPL>(L, blockIdx.y * blockDim.x * CPL, blockIdx.x, blockIdx.z, parity, tab);
+    if constexpr (Codec<F>::kTable && CPL == 1) {
+        // every wavefront fetches its own copy of the (2 KB) table, which
+        // arrives while its DDF loads are in flight: no workgroup barrier.
+        // The copies are dynamic LDS, 2 KB per wavefront of the launch.
+        extern __shared__ __attribute__((aligned(16))) EncEntry s_wave_tabs[];
+        EncEntry(&mine)[kEncEntries] = reinterpret_cast<EncEntry(*)[kEncEntries]>(s_wave_tabs)[threadIdx.x >> 6];
+        fetch_wave_table(enc, mine);
+        step_tile<Q, F, A, COLL, true>(L, blockIdx.y * blockDim.x, blockIdx.x, blockIdx.z, parity, mine);
+    } else {
+        __shared__ EncEntry s_tab[Codec<F>::kTable ? kEncEntries : 1];
+        const EncEntry* tab = stage_table<F>(enc, s_tab);
+        run_tile<Q, F, A, COLL, CPL>(L, blockIdx.y * blockDim.x * CPL, blockIdx.x, blockIdx.z, parity, tab);
+    }
 }
 
 // Ensemble: workgroups walk the tile table (one tile each, or a persistent
@@ -1019,7 +1059,7 @@ template <int Q, int F, class A, int COLL, int CPL>
 __global__ void __launch_bounds__(512) k_step_batched(const LatDev* __restrict__ lats,
                                                       const Tile* __restrict__ tiles, uint32_t ntiles,
                                                       int parity, const EncEntry* __restrict__ enc) {
-    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? kEncEntries : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
@@ -1031,7 +1071,7 @@ template <int Q, int F, class A, int COLL>
 __global__ void __launch_bounds__(512) k_step_dense(const LatDev* __restrict__ lats,
                                                     const Tile* __restrict__ tiles, uint32_t ntiles,
                                                     int parity, const EncEntry* __restrict__ enc) {
-    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? kEncEntries : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = tiles[t];
@@ -1057,7 +1097,7 @@ __device__ __forceinline__ typename Codec<F>::T eq_code(int i, A rho, A ux, A uy
 template <int Q, int F, class A>
 __global__ void __launch_bounds__(64) k_eq_codes(LatDev L, typename Codec<F>::T* __restrict__ out,
                                                  const EncEntry* __restrict__ enc) {
-    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? kEncEntries : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
     const int i = threadIdx.x;
     if (i < Q) out[i] = eq_code<Q, F, A>(i, (A)L.eq_rho, (A)L.eq_u[0], (A)L.eq_u[1], (A)L.eq_u[2], (A)L.shift, tab);
@@ -1071,7 +1111,7 @@ __global__ void __launch_bounds__(256) k_init(LatDev L, const double* __restrict
                                               const double* __restrict__ u_in,
                                               const EncEntry* __restrict__ enc) {
     using T = typename Codec<F>::T;
-    __shared__ EncEntry s_tab[Codec<F>::kTable ? 256 : 1];
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? kEncEntries : 1];
     const EncEntry* tab = stage_table<F>(enc, s_tab);
     const size_t N = (size_t)L.nx * L.ny * L.nz;
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1340,8 +1380,9 @@ struct FormatLaunchers {
     static hipError_t single_cpl(const StepLaunch& s, const LatDev& L) {
         const uint32_t per_wg = (uint32_t)s.block * CPL;
         const uint32_t segs = (L.nx + per_wg - 1) / per_wg;
-        hipLaunchKernelGGL((k_step_single<Q, F, A, COLL, CPL>), dim3(L.ny, segs, L.nz), dim3(s.block), 0, s.stream, L,
-                           s.parity, segs, s.enc);
+        const size_t lds = (Codec<F>::kTable && CPL == 1) ? (size_t)(s.block / 64) * sizeof(EncEntry) * kEncEntries : 0;
+        hipLaunchKernelGGL((k_step_single<Q, F, A, COLL, CPL>), dim3(L.ny, segs, L.nz), dim3(s.block), lds, s.stream,
+                           L, s.parity, segs, s.enc);
         return hipGetLastError();
     }
     template <int Q, class A, int COLL, int CPL>

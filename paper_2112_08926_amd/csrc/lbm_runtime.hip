@@ -66,7 +66,7 @@ static lbm_status device_table(int storage, const EncEntry** out) {
         g_tables.device = dev;
     }
     if (!g_tables.dev[storage]) {
-        EncEntry host[256];
+        EncEntry host[kEncEntries];
         std::string why;
         if (!build_encoder_table(storage, host, &why))
             return fail(LBM_EDEVICE, "encoder table of format %d: %s", storage, why.c_str());
@@ -164,9 +164,9 @@ __global__ void __launch_bounds__(256) k_diag_reduce(const double* __restrict__ 
 __global__ void __launch_bounds__(256) k_encode(int storage, const float* __restrict__ in,
                                                 uint16_t* __restrict__ out, int64_t n,
                                                 const EncEntry* __restrict__ enc) {
-    __shared__ EncEntry s_tab[256];
+    __shared__ EncEntry s_tab[kEncEntries];
     if (enc) {
-        for (int k = threadIdx.x; k < 256; k += blockDim.x) s_tab[k] = enc[k];
+        for (int k = threadIdx.x; k < kEncEntries; k += blockDim.x) s_tab[k] = enc[k];
         __syncthreads();
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) k_encode(int storage, const float* __rest
         case S_FP16: c = Codec<S_FP16>::store<float>(x, nullptr); break;
         case S_FP16S: c = Codec<S_FP16S>::store<float>(x, nullptr); break;
         case S_FP16C: c = Codec<S_FP16C>::store<float>(x, nullptr); break;
-        default: c = table_encode(x, s_tab); break;
+        default: c = table_encode(x, s_tab, enc_window_lo(storage)); break;
         }
         out[i] = c;
     }
@@ -270,16 +270,35 @@ __global__ void __launch_bounds__(256) k_copy(const f32x4* __restrict__ src, f32
 // caller never stores, so the loads cannot be dropped and nothing is
 // written in practice.  A thread that reads nothing keeps acc = 0 and
 // writes nothing, so sink indices stay below n.
+// Each thread handles kMemUnroll elements per pass, issued before any is
+// used, so that enough loads are in flight to cover the memory latency.
+constexpr int kMemUnroll = 8;
 __global__ void __launch_bounds__(256) k_mem_read(const uint32_t* __restrict__ src, uint32_t* __restrict__ sink,
                                                   size_t n, uint32_t shift) {
+    const size_t T = (size_t)gridDim.x * blockDim.x;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t* s = src + shift;
     uint32_t acc = 0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        acc ^= src[i + shift];
-    if (acc == 0x9E3779B9u) sink[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+    size_t i = t;
+    for (; i + (kMemUnroll - 1) * T < n; i += kMemUnroll * T) {
+        uint32_t v[kMemUnroll];
+#pragma unroll
+        for (int k = 0; k < kMemUnroll; k++) v[k] = __builtin_nontemporal_load(s + i + k * T);
+#pragma unroll
+        for (int k = 0; k < kMemUnroll; k++) acc ^= v[k];
+    }
+    for (; i < n; i += T) acc ^= __builtin_nontemporal_load(s + i);
+    if (acc == 0x9E3779B9u) sink[t] = acc;
 }
 __global__ void __launch_bounds__(256) k_mem_write(uint32_t* __restrict__ dst, size_t n, uint32_t shift) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        dst[i + shift] = (uint32_t)i;
+    const size_t T = (size_t)gridDim.x * blockDim.x;
+    uint32_t* d = dst + shift;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kMemUnroll - 1) * T < n; i += kMemUnroll * T) {
+#pragma unroll
+        for (int k = 0; k < kMemUnroll; k++) __builtin_nontemporal_store((uint32_t)(i + k * T), d + i + k * T);
+    }
+    for (; i < n; i += T) __builtin_nontemporal_store((uint32_t)i, d + i);
 }
 
 // ------------------------------------------------------------------ static scratch
@@ -1166,8 +1185,10 @@ extern "C" lbm_status lbm_memory_probe(int32_t kind, const void* d_src, void* d_
     if ((read && !d_src) || !d_dst || (bytes % 4) || ((uintptr_t)d_src % 4) || ((uintptr_t)d_dst % 4) || bytes < 8)
         return fail(LBM_EINVAL, "memory probe needs 4-byte aligned pointers and a size of at least 8, a multiple of 4");
     const size_t n = bytes / 4 - shift;            // elements accessed, shift .. shift + n - 1
+    // a grid of 64 workgroups of 256 threads per CU (enough waves in flight;
+    // each thread then walks the buffer in strides of the whole grid)
     const size_t threads = 256;
-    const size_t blocks = std::min<size_t>((n + threads - 1) / threads, (size_t)1 << 20);
+    const size_t blocks = std::min<size_t>((n + threads - 1) / threads, (size_t)64 * 256);
     if (read) {
         hipLaunchKernelGGL(k_mem_read, dim3((unsigned)blocks), dim3(threads), 0, (hipStream_t)stream,
                            (const uint32_t*)d_src, (uint32_t*)d_dst, n, shift);

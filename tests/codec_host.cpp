@@ -1,0 +1,45 @@
+// Host build of the library's codec header (the same decoders and encoder
+// table the kernels use), for a CPU comparison with the oracle:
+//   codec_host <format index> <decoded.bin> <inputs.bin> <codes.bin>
+// writes the FP32 value of every 16-bit code, then encodes the FP32 inputs.
+// Format indices are the library's storage enum (FP16 2 ... P16_2C 7).
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "lbm_enc_table.h"
+
+int main(int argc, char** argv) {
+    if (argc != 5) return 2;
+    const int fmt = std::atoi(argv[1]);
+    std::vector<float> dec(65536);
+    for (uint32_t c = 0; c < 65536; c++) dec[c] = lbm::decode16(fmt, c);
+    FILE* f = std::fopen(argv[2], "wb");
+    if (!f || std::fwrite(dec.data(), 4, dec.size(), f) != dec.size()) return 3;
+    std::fclose(f);
+    f = std::fopen(argv[3], "rb");
+    if (!f) return 4;
+    std::vector<float> in;
+    float x;
+    while (std::fread(&x, 4, 1, f) == 1) in.push_back(x);
+    std::fclose(f);
+    std::vector<uint16_t> out(in.size());
+    if (fmt >= lbm::S_P16_0S) {
+        std::vector<lbm::EncEntry> tab(lbm::kEncEntries);
+        std::string why;
+        if (!lbm::build_encoder_table(fmt, tab.data(), &why)) {
+            std::fprintf(stderr, "table: %s\n", why.c_str());
+            return 5;
+        }
+        for (size_t i = 0; i < in.size(); i++) out[i] = lbm::table_encode(in[i], tab.data(), lbm::enc_window_lo(fmt));
+    } else if (fmt == lbm::S_FP16C) {
+        for (size_t i = 0; i < in.size(); i++) out[i] = lbm::fp16c_encode(in[i]);
+    } else {
+        return 6;
+    }
+    f = std::fopen(argv[4], "wb");
+    if (!f || std::fwrite(out.data(), 2, out.size(), f) != out.size()) return 7;
+    std::fclose(f);
+    return 0;
+}
