@@ -33,6 +33,17 @@ namespace lbm {
 __host__ __device__ __forceinline__ uint32_t f2u(float x) { return __builtin_bit_cast(uint32_t, x); }
 __host__ __device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit_cast(float, u); }
 
+// Small integer helpers (one instruction each on the device).
+__host__ __device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__host__ __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__host__ __device__ __forceinline__ uint32_t ubfe(uint32_t v, uint32_t off, uint32_t width) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_ubfe(v, off, width);
+#else
+    return (v >> off) & ((1u << width) - 1u);
+#endif
+}
+
 // ---------------------------------------------------------------- FP16C
 // 1 sign | 4 exponent (bias 15) | 11 mantissa, no Inf/NaN.  Placing the 15
 // magnitude bits at FP32 bits 26..12 gives 2^(e-127)(1 + m/2^11), or the FP32
@@ -51,13 +62,22 @@ __host__ __device__ __forceinline__ float fp16c_decode(uint32_t c) {
 // |x| >= 2^-14: the FP32 bits rebiased by 112 in the exponent, rounded at
 // the 12th bit (a carry moves to the next binade by itself).  Below: the
 // denormal codes are the multiples of 2^-25, so the code is |x| 2^25 rounded
-// half up (exact in float except just below 0.5, where y + 0.5 would round
-// to 1: those round to 0).  Checked against the exact table encoder on all
-// 2^32 floats.
+// half up.  On the device both are computed and one selected (no branch);
+// the half-up rounding is one v_cvt_rpi_i32_f32 (round to nearest, ties
+// towards +infinity).  The host rounds y + 0.5 down, which is exact in
+// float except just below 0.5, where y + 0.5 would round to 1: those round
+// to 0.  Checked against the oracle's nearest-code encoder on all 2^32
+// floats (device) and on every code boundary (host).
 __host__ __device__ __forceinline__ uint16_t fp16c_encode(float x) {
     const uint32_t b = f2u(x);
     const uint32_t a = b & 0x7FFFFFFFu;
     uint32_t code;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t cn = umin((a - (112u << 23) + 0x800u) >> 12, 0x7FFFu);
+    int32_t cd;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(cd) : "v"(u2f(a) * 0x1p25f));
+    code = a >= (113u << 23) ? cn : (uint32_t)cd;
+#else
     if (a >= (113u << 23)) {
         code = (a - (112u << 23) + 0x800u) >> 12;
         code = code < 0x7FFFu ? code : 0x7FFFu;
@@ -65,6 +85,7 @@ __host__ __device__ __forceinline__ uint16_t fp16c_encode(float x) {
         const float y = u2f(a) * 0x1p25f;
         code = y < 0.5f ? 0u : (uint32_t)(y + 0.5f);
     }
+#endif
     return (uint16_t)(((b >> 16) & 0x8000u) | code);
 }
 
@@ -177,16 +198,6 @@ __host__ __device__ __forceinline__ float half_decode(uint32_t c) {
 }
 __host__ __device__ __forceinline__ uint16_t half_encode(float x) {
     return __builtin_bit_cast(uint16_t, (_Float16)x);
-}
-
-__host__ __device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
-__host__ __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
-__host__ __device__ __forceinline__ uint32_t ubfe(uint32_t v, uint32_t off, uint32_t width) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_ubfe(v, off, width);
-#else
-    return (v >> off) & ((1u << width) - 1u);
-#endif
 }
 
 // First FP32 exponent field of a posit format's encoder window: two binades
