@@ -86,25 +86,34 @@ def time_steps(g, steps, warmup):
 
 
 def diag_cost(g, flags, q, storage, every, steps):
-    """Cost of the FP64 diagnostics (lbm_diagnostics: both reduction passes
-    and the copy of the results to the host, which synchronises): the time
-    of one call measured with events on the handle's stream, its algorithmic
-    bytes (Q b + 1 per fluid cell, the flag byte per other cell) per second,
-    and the wall-clock overhead per step of calling it every `every` steps
-    over `steps` steps, against the same steps without it."""
+    """Cost of the FP64 diagnostics.  The separate pass (lbm_diagnostics:
+    first pass, both reduction passes and the copy of the results to the
+    host, which synchronises): the time of one call measured with events on
+    the handle's stream and its algorithmic bytes (Q b + 1 per fluid cell,
+    the flag byte per other cell) per second.  The fused step
+    (lbm_step_diagnostics: a step that also reduces the state it reads): its
+    time against a plain step.  And the wall-clock overhead per step of
+    taking the diagnostics every `every` steps with the fused step, over
+    `steps` steps, against the same steps without them."""
     import torch
     stream = g.stream
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    times = []
-    for _ in range(5):
-        e0.record(stream)
-        d = g.diagnostics(0)
-        e1.record(stream)
+
+    def timed(fn, reps=5):
         torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    ms = float(np.median(times))
+        out, times = None, []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return float(np.median(times)), out
+
+    ms, d = timed(lambda: g.diagnostics(0))
+    fused_ms, _ = timed(lambda: g.step_diagnostics())
+    step_ms, _ = timed(lambda: g.step(1))
     N = flags.size
     n_fluid = int(np.count_nonzero(flags == 0))
     alg = n_fluid * (q * ddf_bytes(storage) + 1) + (N - n_fluid)
@@ -115,13 +124,15 @@ def diag_cost(g, flags, q, storage, every, steps):
     plain = time.perf_counter() - t0
     t0 = time.perf_counter()
     for _ in range(steps // every):
-        g.step(every)
-        d = g.diagnostics(0)
+        g.step(every - 1)
+        d = g.step_diagnostics()
     g.synchronize()
     with_diag = time.perf_counter() - t0
     return {"every": every, "diag_ms": round(ms, 4), "diag_alg_bytes": alg,
-            "diag_GBps": round(alg / (ms * 1e-3) / 1e9, 1), "diag_frac_of_8TBps": round(alg / (ms * 1e-3) / 1e9 /
-                                                                                         HBM_PEAK_GBS, 4),
+            "diag_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+            "diag_frac_of_8TBps": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "fused_step_ms": round(fused_ms, 4), "plain_step_ms": round(step_ms, 4),
+            "fused_extra_ms": round(fused_ms - step_ms, 4),
             "overhead_ms_per_step": round((with_diag - plain) / steps * 1e3, 4),
             "plain_ms_per_step": round(plain / steps * 1e3, 4),
             "last": {"kinetic_energy": d["kinetic_energy"], "mass": d["mass"],

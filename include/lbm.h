@@ -232,6 +232,22 @@ lbm_status lbm_get_ddf(lbm_handle* h, int32_t lattice, void* host);
  * u_ref), LBM_EDEVICE. */
 lbm_status lbm_diagnostics(lbm_handle* h, int32_t lattice, const double* u_ref, lbm_diag* out);
 
+/* One time step fused with the diagnostics of the state it reads (the
+ * paper's runs sample the kinetic energy of Sec. 4.2 or the drag and lift of
+ * Sec. 4.3 every few steps): the step's kernel pulls each cell once for both,
+ * so a diagnostic step costs little more than a plain one.  *out is
+ * bit-identical to lbm_diagnostics called before the step (out->step is the
+ * step number of that state), the DDFs written to a plain lbm_step; the
+ * handle has advanced one step on return, and out->nonfinite_updates
+ * includes the step just taken.  u_ref_dev: NULL or a DEVICE array of 3*N
+ * doubles laid out as lbm_diagnostics' u_ref (owned by the caller).  Runs
+ * with workgroups of 512 threads whatever the launch configuration, outside
+ * any captured graph.  Allocates nothing.  Synchronises.  Returns
+ * LBM_ENONFINITE (after filling *out and stepping) like lbm_diagnostics.
+ * Errors: LBM_EINVAL (NULL handle or out), LBM_EUNSUPPORTED (a handle of
+ * more than one lattice), LBM_EDEVICE. */
+lbm_status lbm_step_diagnostics(lbm_handle* h, const double* u_ref_dev, lbm_diag* out);
+
 /* For callers that cannot allocate device memory (code around a HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the
  * diagnostics of lbm_diagnostics without any allocation.  u_ref_dev: NULL

@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     PROBE, STORAGE, LbmDiag, LbmError, LbmInfo, LbmLaunch, LbmParams, Lattices, lbm_autotune,
     lbm_copy_probe, lbm_create, lbm_decode, lbm_destroy, lbm_diagnostics, lbm_diagnostics_noalloc, lbm_encode,
     lbm_get_ddf, lbm_get_launch, lbm_get_rho_u, lbm_info_get, lbm_last_error, lbm_memory_probe, lbm_set_boundaries,
+    lbm_step_diagnostics,
     lbm_set_ddf, lbm_set_launch, lbm_set_rho_u, lbm_step, lbm_synchronize, library, library_id, library_path,
     make_params,
 )

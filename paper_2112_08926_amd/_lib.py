@@ -106,6 +106,7 @@ def library():
         "lbm_set_ddf": (S, [_P, ctypes.c_int32, _P]),
         "lbm_get_ddf": (S, [_P, ctypes.c_int32, _P]),
         "lbm_diagnostics": (S, [_P, ctypes.c_int32, _P, ctypes.POINTER(LbmDiag)]),
+        "lbm_step_diagnostics": (S, [_P, _P, ctypes.POINTER(LbmDiag)]),
         "lbm_diagnostics_noalloc": (S, [_P, ctypes.c_int32, _P, ctypes.POINTER(LbmDiag)]),
         "lbm_set_launch": (S, [_P, ctypes.POINTER(LbmLaunch)]),
         "lbm_get_launch": (S, [_P, ctypes.POINTER(LbmLaunch)]),
@@ -270,6 +271,17 @@ def lbm_diagnostics(h, lattice: int, N: int, u_ref: np.ndarray | None = None) ->
     return d
 
 
+def lbm_step_diagnostics(h, u_ref_dev: int | None = None) -> LbmDiag:
+    """One step fused with the diagnostics of the state it reads (a handle
+    of one lattice); u_ref_dev: None or the device address of 3*N doubles.
+    Raises like lbm_diagnostics."""
+    d = LbmDiag()
+    rc = library().lbm_step_diagnostics(h, u_ref_dev, ctypes.byref(d))
+    if rc not in (0, -5):
+        _check(rc)
+    return d
+
+
 def lbm_diagnostics_noalloc(h, lattice: int, u_ref_dev: int | None = None) -> LbmDiag:
     """lbm_diagnostics without allocation; u_ref_dev: None or the device
     address of 3*N doubles (e.g. a torch tensor's data_ptr()).  Raises like
@@ -374,6 +386,10 @@ class Lattices:
 
     def diagnostics(self, k: int = 0, u_ref=None) -> dict:
         return lbm_diagnostics(self.h, k, self.N(k), u_ref).as_dict()
+
+    def step_diagnostics(self, u_ref_dev: int | None = None) -> dict:
+        """One step, returning the diagnostics of the state it read."""
+        return lbm_step_diagnostics(self.h, u_ref_dev).as_dict()
 
     def set_launch(self, mode=None, block=None, cells_per_lane=None, persistent=None, graph_steps=None):
         c = lbm_get_launch(self.h)

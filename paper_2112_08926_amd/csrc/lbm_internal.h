@@ -83,6 +83,8 @@ hipError_t launch_eq_codes(int q, int storage, int arith, const LatDev& lat, voi
 #define LBM_DECLARE_FORMAT(NAME)                                                              \
     hipError_t step_single_##NAME(const StepLaunch& s, const LatDev& lat);                   \
     hipError_t step_batched_##NAME(const StepLaunch& s);                                     \
+    hipError_t step_diag_##NAME(const StepLaunch& s, const LatDev& lat, const double* u_ref, \
+                                double* partials, uint32_t segs);                            \
     hipError_t init_##NAME(int q, int arith, const LatDev& lat, const double* rho,           \
                            const double* u, const EncEntry* enc, hipStream_t st);            \
     hipError_t moments_##NAME(int q, int arith, const LatDev& lat, int parity, double* rho,  \

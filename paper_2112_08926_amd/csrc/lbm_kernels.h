@@ -1221,26 +1221,69 @@ __device__ __forceinline__ double wave_reduce(double v) {
     return v;
 }
 
+// Pairwise sums across the wavefront's halves (lanes i and i + 32) of two
+// fields at once: lanes 0-31 get a's, lanes 32-63 b's (one v_permlane32_swap
+// per 32-bit half of the doubles, one add).
+__device__ __forceinline__ double comb32(double a, double b) {
+    const uint64_t ab = __builtin_bit_cast(uint64_t, a), bb = __builtin_bit_cast(uint64_t, b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ab, (uint32_t)bb, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ab >> 32), (uint32_t)(bb >> 32), false, false);
+    const double a2 = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+    const double b2 = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+    return a2 + b2;
+}
+// The same across neighbouring rows of 16 lanes: rows 0 and 2 keep a's sums
+// of rows (0,1) and (2,3), rows 1 and 3 get b's.
+__device__ __forceinline__ double comb16(double a, double b) {
+    const uint64_t ab = __builtin_bit_cast(uint64_t, a), bb = __builtin_bit_cast(uint64_t, b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ab, (uint32_t)bb, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ab >> 32), (uint32_t)(bb >> 32), false, false);
+    const double a2 = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+    const double b2 = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+    return a2 + b2;
+}
+// Four fields summed over the wavefront, one per row of 16 lanes: row 0
+// f0, row 1 f2, row 2 f1, row 3 f3 (every lane of a row holds its total).
+__device__ __forceinline__ double reduce4(double f0, double f1, double f2, double f3) {
+    constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+    double v = comb16(comb32(f0, f1), comb32(f2, f3));
+    v += dpp_f64<kXor1>(v);
+    v += dpp_f64<kXor2>(v);
+    v += dpp_f64<kHalfMirror>(v);
+    v += dpp_f64<kMirror>(v);
+    return v;
+}
+
 // Block-wide reduction of kDiagFields values (the last one by max, of
 // non-negative values) in a fixed order, without a barrier at the end: each
-// wavefront reduces its values with DPP and puts them in its LDS slot
-// (fields absent in the wavefront -- bit k of the wavefront-uniform `skip`
-// -- as 0), then counts itself in; the wavefront that counts last sums the
-// slots in wavefront order (lane k field k) and writes out[k].  The others
-// leave as soon as they have counted, instead of waiting for the slowest.
-// `count` must be zero at entry for the whole workgroup (set before a
-// barrier at the start of the kernel).
+// wavefront reduces its values -- the sums four fields at a time, one field
+// per row of 16 lanes after two cross-lane swaps (reduce4), the max with DPP
+// -- and puts them in its LDS slot (the wall force only in wavefronts next
+// to a wall, bit 7 of the wavefront-uniform `skip`; 0 otherwise), then counts
+// itself in; the wavefront that counts last sums the slots in wavefront
+// order (lane k field k) and writes out[k].  The others leave as soon as they
+// have counted, instead of waiting for the slowest.  `count` must be zero at
+// entry for the whole workgroup (set before a barrier at the start of the
+// kernel).
 __device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], uint32_t skip, double* out,
                                                    uint32_t* count) {
     constexpr int kMaxWaves = 1024 / 64;
     __shared__ double s[kDiagFields][kMaxWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int k = 0; k < kDiagFields; k++) {
-        double v = 0.0;
-        if (!((skip >> k) & 1u)) v = k == kDiagFields - 1 ? wave_reduce<true>(acc[k]) : wave_reduce<false>(acc[k]);
-        if (lane == 63) s[k][wave] = v;
+    const int row = lane >> 4;
+    const bool last_of_row = (lane & 15) == 15;
+    // rows of reduce4's result: f0, f2, f1, f3
+    const double g1 = reduce4(acc[0], acc[1], acc[2], acc[3]);
+    const double g2 = reduce4(acc[4], acc[10], acc[5], acc[6]);
+    if (last_of_row) {
+        s[row == 0 ? 0 : row == 1 ? 2 : row == 2 ? 1 : 3][wave] = g1;
+        s[row == 0 ? 4 : row == 1 ? 5 : row == 2 ? 10 : 6][wave] = g2;
     }
+    double g3 = 0.0;
+    if (!((skip >> 7) & 1u)) g3 = reduce4(acc[7], acc[8], acc[9], 0.0);
+    if (last_of_row && row != 3) s[row == 0 ? 7 : row == 1 ? 9 : 8][wave] = g3;
+    const double mx = wave_reduce<true>(acc[kDiagFields - 1]);
+    if (lane == 63) s[kDiagFields - 1][wave] = mx;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     uint32_t before = 0;
     if (lane == 0) before = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1359,12 +1402,68 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(LatDev L, int parity, con
         pull<Q, F, A, false>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
         diag_cell<Q, F, A>(L, src, fl, x, y, z, n, f, u_ref, v);
     }
-    // fields no cell of this wavefront has: the reference norms without u_ref,
-    // the wall force away from walls, the non-finite count if all are finite
-    uint32_t skip = 0;
-    if (!u_ref) skip |= (1u << 5) | (1u << 6);
-    if (!__any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0)) skip |= (1u << 7) | (1u << 8) | (1u << 9);
-    if (!__any(v[10] != 0.0)) skip |= 1u << 10;
+    // the wall force is reduced only by wavefronts next to a wall
+    const uint32_t skip = __any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0) ? 0u : (1u << 7);
+    block_reduce_store(v, skip, partials + ((size_t)(z * L.ny + y) * segs + seg) * kDiagFields, &waves_done);
+}
+
+// One time step fused with the diagnostics of the state it reads: the row
+// tiles of k_diag (kDiagThreads cells of one row per workgroup, grid (ny,
+// segs, nz)), each lane pulling its cell once for both.  The pulled DDFs,
+// scaled from the step's raw units (a power of two, exact), give diag_cell
+// exactly the values k_diag's own pull gives, and the workgroup reduces them
+// in k_diag's order into the same partial slot, so the diagnostics are
+// bit-identical to k_diag on the same state; the DDFs written are the
+// step's.  Lanes past the row's end step the row's last cell, store nothing
+// and add nothing (every lane takes part in the cross-lane reduction).
+template <int Q, int F, class A, int COLL>
+__global__ void __launch_bounds__(kDiagThreads) k_step_diag(LatDev L, int parity, uint32_t segs,
+                                                            const EncEntry* __restrict__ enc,
+                                                            const double* __restrict__ u_ref,
+                                                            double* __restrict__ partials) {
+    using T = typename Codec<F>::T;
+    __shared__ uint32_t waves_done;
+    __shared__ EncEntry s_tab[Codec<F>::kTable ? kEncEntries : 1];
+    if (threadIdx.x == 0) waves_done = 0;
+    const EncEntry* tab = nullptr;
+    if constexpr (Codec<F>::kTable) tab = stage_table<F>(enc, s_tab);     // its barrier also publishes waves_done
+    else __syncthreads();
+    const uint32_t y = blockIdx.x, seg = blockIdx.y, z = blockIdx.z;
+    const bool active = seg * kDiagThreads + threadIdx.x < L.nx;
+    const uint32_t x = active ? seg * kDiagThreads + threadIdx.x : L.nx - 1;
+    RowCtx rc;
+    make_rows(L, y, z, rc);
+    const uint32_t n = rc.rows[4] + x;
+    const uint8_t fl = ld_off(L.flags, n);
+    const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
+    const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+    const T* __restrict__ src = (const T*)L.f[parity];
+    T* __restrict__ dst = (T*)L.f[parity ^ 1];
+
+    A f[Q], fo[Q];
+    const bool special = (fl & (F_SOLID | F_EQ)) != 0;
+    pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
+    double v[kDiagFields];
+#pragma unroll
+    for (int k = 0; k < kDiagFields; k++) v[k] = 0.0;
+    if (active) {
+        constexpr A kUnraw = (A)(1.0 / exp2i(Codec<F>::kRawExp));
+        A fd[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) fd[i] = f[i] * kUnraw;
+        diag_cell<Q, F, A>(L, src, fl, x, y, z, n, fd, u_ref, v);
+    }
+    bool bad;
+    collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
+    count_nonfinite(L, bad && !special && active);
+    T c[Q];
+    out_codes<Q, F, A>(L, fl, fo, tab, c);
+    const size_t plane = L.plane;
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) st_off(dst + ((size_t)i * plane + rc.rows[4]), x, c[i]);
+    }
+    const uint32_t skip = __any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0) ? 0u : (1u << 7);
     block_reduce_store(v, skip, partials + ((size_t)(z * L.ny + y) * segs + seg) * kDiagFields, &waves_done);
 }
 
@@ -1411,6 +1510,13 @@ struct FormatLaunchers {
                 if (s.cpl == 4) return single_cpl<Q, A, COLL, 4>(s, L);
         }
         return hipErrorInvalidValue;
+    }
+    template <int Q, class A, int COLL>
+    static hipError_t step_diag_qac(const StepLaunch& s, const LatDev& L, const double* u_ref, double* partials,
+                                    uint32_t segs) {
+        hipLaunchKernelGGL((k_step_diag<Q, F, A, COLL>), dim3(L.ny, segs, L.nz), dim3(kDiagThreads), 0, s.stream, L,
+                           s.parity, segs, s.enc, u_ref, partials);
+        return hipGetLastError();
     }
     template <int Q, class A, int COLL>
     static hipError_t batched_qac(const StepLaunch& s) {

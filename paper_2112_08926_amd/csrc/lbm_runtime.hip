@@ -924,7 +924,11 @@ extern "C" lbm_status lbm_get_ddf(lbm_handle* h, int32_t k, void* host) {
 // passes, then the results and the lattice's count of non-finite updates to
 // the host.  `work`: device memory of at least diag_doubles() doubles for
 // the partials and results.  Synchronises.  d_ref: device u_ref or null.
-static lbm_status run_diagnostics(lbm_handle* h, int32_t k, const double* d_ref, double* work, lbm_diag* out) {
+// with_step: the first pass is the fused step (k_step_diag) instead of
+// k_diag: the diagnostics are those of the state the step reads, and the
+// handle has advanced one step when this returns.
+static lbm_status run_diagnostics(lbm_handle* h, int32_t k, const double* d_ref, double* work, lbm_diag* out,
+                                  bool with_step = false) {
     Lattice& L = h->lats[k];
     const DiagLayout dl = diag_layout(L);
     double* partials = work;
@@ -933,19 +937,40 @@ static lbm_status run_diagnostics(lbm_handle* h, int32_t k, const double* d_ref,
     const uint32_t segs = dl.segs;
     double res[kDiagFields];
     unsigned long long nonfinite_updates = 0;
+    const int64_t step = h->step;
     hipError_t e;
-#define E(N) diag_##N(h->q, h->arith, L.dev, h->parity, d_ref, partials, segs, h->stream)
-    switch (h->storage) {
-    case S_FP64: e = E(fp64); break;
-    case S_FP32: e = E(fp32); break;
-    case S_FP16: e = E(fp16); break;
-    case S_FP16S: e = E(fp16s); break;
-    case S_FP16C: e = E(fp16c); break;
-    case S_P16_0S: e = E(p16_0s); break;
-    case S_P16_1S: e = E(p16_1s); break;
-    default: e = E(p16_2c); break;
-    }
+    if (with_step) {
+        const StepLaunch s = make_launch(h, h->launch, h->parity);
+#define E(N) step_diag_##N(s, L.dev, d_ref, partials, segs)
+        switch (h->storage) {
+        case S_FP64: e = E(fp64); break;
+        case S_FP32: e = E(fp32); break;
+        case S_FP16: e = E(fp16); break;
+        case S_FP16S: e = E(fp16s); break;
+        case S_FP16C: e = E(fp16c); break;
+        case S_P16_0S: e = E(p16_0s); break;
+        case S_P16_1S: e = E(p16_1s); break;
+        default: e = E(p16_2c); break;
+        }
 #undef E
+        if (e == hipSuccess) {
+            h->parity ^= 1;
+            h->step += 1;
+        }
+    } else {
+#define E(N) diag_##N(h->q, h->arith, L.dev, h->parity, d_ref, partials, segs, h->stream)
+        switch (h->storage) {
+        case S_FP64: e = E(fp64); break;
+        case S_FP32: e = E(fp32); break;
+        case S_FP16: e = E(fp16); break;
+        case S_FP16S: e = E(fp16s); break;
+        case S_FP16C: e = E(fp16c); break;
+        case S_P16_0S: e = E(p16_0s); break;
+        case S_P16_1S: e = E(p16_1s); break;
+        default: e = E(p16_2c); break;
+        }
+#undef E
+    }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_diag_reduce, dim3(dl.groups), dim3(256), 0, h->stream, partials, dl.tiles, dl.chunk,
                            groups);
@@ -972,7 +997,7 @@ static lbm_status run_diagnostics(lbm_handle* h, int32_t k, const double* d_ref,
     out->force_on_solid[2] = res[9];
     out->nonfinite_cells = (int64_t)res[10];
     out->u_max = std::sqrt(res[11]);
-    out->step = h->step;
+    out->step = step;
     out->nonfinite_updates = (int64_t)nonfinite_updates;
     if (out->nonfinite_cells > 0 || out->nonfinite_updates > 0)
         return fail(LBM_ENONFINITE, "lattice %d: %lld fluid cells with non-finite fields now, %lld cell updates "
@@ -999,6 +1024,15 @@ extern "C" lbm_status lbm_diagnostics(lbm_handle* h, int32_t k, const double* u_
     st = run_diagnostics(h, k, d_ref, h->d_partials, out);
     dev_free(h, d_ref);
     return st;
+}
+
+extern "C" lbm_status lbm_step_diagnostics(lbm_handle* h, const double* u_ref_dev, lbm_diag* out) {
+    if (!h) return fail(LBM_EINVAL, "handle is NULL");
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    if (h->lats.size() != 1)
+        return fail(LBM_EUNSUPPORTED, "lbm_step_diagnostics steps a handle of one lattice (this one has %zu)",
+                    h->lats.size());
+    return run_diagnostics(h, 0, u_ref_dev, h->d_partials, out, true);
 }
 
 extern "C" lbm_status lbm_diagnostics_noalloc(lbm_handle* h, int32_t k, const double* u_ref_dev, lbm_diag* out) {

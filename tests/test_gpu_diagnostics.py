@@ -30,9 +30,9 @@ def lbm():
 @pytest.mark.parametrize("q,collision", [(19, "trt"), (27, "srt")])
 @pytest.mark.parametrize("storage", FORMATS)
 def test_diagnostics_of_a_stored_state(lbm, orc, storage, q, collision):
-    """600 x 40 x 30 cells: rows of three 256-cell tiles (the last ragged) and
-    3600 row tiles, more than the 2048 workgroups of the first pass, so
-    workgroups stride over several tiles."""
+    """600 x 40 x 30 cells: rows of two 512-cell segments (the second
+    ragged), 2400 row tiles, more than the 512 workgroups of the second
+    reduction pass, so each of those sums five tiles."""
     nx, ny, nz = 600, 40, 30
     N = nx * ny * nz
     say("diagnostics", storage, q, collision)
