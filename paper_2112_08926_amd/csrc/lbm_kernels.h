@@ -1288,12 +1288,13 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], u
     uint32_t before = 0;
     if (lane == 0) before = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     before = (uint32_t)__builtin_amdgcn_readfirstlane((int)before);
-    if (before != (uint32_t)nwaves - 1) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (lane < kDiagFields) {
-        double v = s[lane][0];
-        for (int w = 1; w < nwaves; w++) v = (lane == kDiagFields - 1) ? fmax(v, s[lane][w]) : v + s[lane][w];
-        out[lane] = v;
+    if (before == (uint32_t)nwaves - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane < kDiagFields) {
+            double v = s[lane][0];
+            for (int w = 1; w < nwaves; w++) v = (lane == kDiagFields - 1) ? fmax(v, s[lane][w]) : v + s[lane][w];
+            out[lane] = v;
+        }
     }
 }
 
@@ -1301,14 +1302,23 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], u
 // f, added to v: mass, momentum, kinetic energy, the error norms against
 // u_ref, the momentum exchange into walls, the non-finite count and the
 // largest |u|^2.  The moments are those the next step sees after streaming
-// (velocity with F/2, not clamped), in the step's arithmetic.
-template <int Q, int F, class A>
+// (velocity with F/2, not clamped), in the step's arithmetic.  RAWE: f in
+// units of 2^-RAWE (the step's raw units); the sums are taken in those units
+// and scaled back, a power of two, so rho and j are bit-identical to sums of
+// the unscaled values.
+template <int Q, int F, class A, int RAWE = 0>
 __device__ __forceinline__ void diag_cell(const LatDev& L, const typename Codec<F>::T* __restrict__ src, uint32_t fl,
                                           uint32_t x, uint32_t y, uint32_t z, uint32_t n, const A (&f)[Q],
                                           const double* __restrict__ u_ref, double (&v)[kDiagFields]) {
     if (fl & (F_SOLID | F_EQ)) return;
     A rho, j[3];
-    fields<Q, A>(f, (A)L.shift, rho, j);
+    fields<Q, A>(f, (A)(L.shift * exp2i(RAWE)), rho, j);
+    if constexpr (RAWE != 0) {
+        constexpr A kUnraw = (A)(1.0 / exp2i(RAWE));
+        rho *= kUnraw;
+#pragma unroll
+        for (int a = 0; a < 3; a++) j[a] *= kUnraw;
+    }
     if (L.forced) {
 #pragma unroll
         for (int a = 0; a < 3; a++) j[a] += (A)0.5 * (A)L.force[a];
@@ -1399,8 +1409,8 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(LatDev L, int parity, con
         const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
         const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
         A f[Q];
-        pull<Q, F, A, false>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
-        diag_cell<Q, F, A>(L, src, fl, x, y, z, n, f, u_ref, v);
+        pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);   // the step's raw units
+        diag_cell<Q, F, A, Codec<F>::kRawExp>(L, src, fl, x, y, z, n, f, u_ref, v);
     }
     // the wall force is reduced only by wavefronts next to a wall
     const uint32_t skip = __any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0) ? 0u : (1u << 7);
@@ -1411,7 +1421,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(LatDev L, int parity, con
 // tiles of k_diag (kDiagThreads cells of one row per workgroup, grid (ny,
 // segs, nz)), each lane pulling its cell once for both.  The pulled DDFs,
 // scaled from the step's raw units (a power of two, exact), give diag_cell
-// exactly the values k_diag's own pull gives, and the workgroup reduces them
+// exactly the sums k_diag's own pull gives, and the workgroup reduces them
 // in k_diag's order into the same partial slot, so the diagnostics are
 // bit-identical to k_diag on the same state; the DDFs written are the
 // step's.  Lanes past the row's end step the row's last cell, store nothing
@@ -1443,15 +1453,14 @@ __global__ void __launch_bounds__(kDiagThreads) k_step_diag(LatDev L, int parity
     A f[Q], fo[Q];
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
     pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
-    double v[kDiagFields];
+    {
+        // the diagnostics first, so that their registers are free for the collision
+        double v[kDiagFields];
 #pragma unroll
-    for (int k = 0; k < kDiagFields; k++) v[k] = 0.0;
-    if (active) {
-        constexpr A kUnraw = (A)(1.0 / exp2i(Codec<F>::kRawExp));
-        A fd[Q];
-#pragma unroll
-        for (int i = 0; i < Q; i++) fd[i] = f[i] * kUnraw;
-        diag_cell<Q, F, A>(L, src, fl, x, y, z, n, fd, u_ref, v);
+        for (int k = 0; k < kDiagFields; k++) v[k] = 0.0;
+        if (active) diag_cell<Q, F, A, Codec<F>::kRawExp>(L, src, fl, x, y, z, n, f, u_ref, v);
+        const uint32_t skip = __any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0) ? 0u : (1u << 7);
+        block_reduce_store(v, skip, partials + ((size_t)(z * L.ny + y) * segs + seg) * kDiagFields, &waves_done);
     }
     bool bad;
     collide<Q, COLL, A, (sizeof(T) >= 4), Codec<F>::kRawExp>(L, f, fo, bad);
@@ -1463,8 +1472,6 @@ __global__ void __launch_bounds__(kDiagThreads) k_step_diag(LatDev L, int parity
 #pragma unroll
         for (int i = 0; i < Q; i++) st_off(dst + ((size_t)i * plane + rc.rows[4]), x, c[i]);
     }
-    const uint32_t skip = __any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0) ? 0u : (1u << 7);
-    block_reduce_store(v, skip, partials + ((size_t)(z * L.ny + y) * segs + seg) * kDiagFields, &waves_done);
 }
 
 // ------------------------------------------------------------ host launchers
