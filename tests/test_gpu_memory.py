@@ -58,3 +58,27 @@ def test_sixteen_bit_footprint_reduction(lbm):
     paper = 1 - paper_bytes("fp32", 2, 19) / paper_bytes("fp32", 4, 19)
     assert abs(paper - 0.45) < 0.01
     assert 0.47 < 1 - fp16 / fp32 < 0.49, (fp32, fp16)
+
+
+def test_device_bytes_stay_exact_through_relaunches(lbm):
+    """The handle's device-memory figure follows its allocations: switching
+    between launch kinds (each builds a tile table and frees the old one) and
+    autotuning (tens of tables) leave it where the same configuration had it
+    before, so nothing is counted twice or leaked."""
+    p = lbm.make_params(96, 64, 48, q=19, storage="fp16s")
+    with lbm.Lattices(p) as g:
+        g.set_launch(mode=0, block=512)
+        base = g.info()["device_bytes"]
+        g.set_launch(mode=2, block=256)
+        dense = g.info()["device_bytes"]
+        assert dense != base             # a table of 256-cell runs replaced one of 512-cell row tiles
+        for _ in range(5):
+            g.set_launch(mode=0, block=512)
+            assert g.info()["device_bytes"] == base
+            g.set_launch(mode=2, block=256)
+            assert g.info()["device_bytes"] == dense
+        g.autotune(2)
+        g.set_launch(mode=2, block=256, cells_per_lane=1, persistent=0)
+        assert g.info()["device_bytes"] == dense
+        g.set_launch(mode=0, block=512)
+        assert g.info()["device_bytes"] == base
