@@ -69,20 +69,26 @@ def cavity(n, storage, tau=0.6, lid=0.1, q=19, collision="trt"):
     return g, flags
 
 
-def time_steps(g, steps, warmup):
+def time_steps(g, steps, warmup, chunks=None):
     """Average time of one step (= one stream-collide launch) over `steps`
-    launches, measured with events on the stream the kernels run on."""
+    launches, measured with events on the stream the kernels run on.  With a
+    list `chunks`, the timed steps are also split into 5 equal runs (when
+    `steps` is a multiple of 5) whose ms per step are appended to it, events
+    only, so the total is timed exactly as without."""
     import torch
     stream = g.stream
     g.step(warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    g.step(steps)
-    e1.record(stream)
+    parts = 5 if (chunks is not None and steps % 5 == 0) else 1
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(parts + 1)]
+    ev[0].record(stream)
+    for k in range(parts):
+        g.step(steps // parts)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    if parts > 1:
+        chunks.extend(ev[k].elapsed_time(ev[k + 1]) / (steps // parts) for k in range(parts))
+    return ev[0].elapsed_time(ev[parts]) / steps
 
 
 def diag_cost(g, flags, q, storage, every, steps):
@@ -145,7 +151,8 @@ def measure_format(storage, n, steps, warmup, diag_every=0):
     try:
         g.step(2)
         cfg = g.autotune(5)                      # leaves the state unchanged
-        ms = time_steps(g, steps, warmup)
+        chunks = []
+        ms = time_steps(g, steps, warmup, chunks)
         d = g.diagnostics(0)
         diag = diag_cost(g, flags, 19, storage, diag_every, 5 * diag_every) if diag_every else None
     finally:
@@ -160,7 +167,10 @@ def measure_format(storage, n, steps, warmup, diag_every=0):
             "achieved_GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
             "kinetic_energy": d["kinetic_energy"], "nonfinite": d["nonfinite_cells"],
             "nonfinite_updates": d["nonfinite_updates"],
-            "launch": {k: cfg[k] for k in ("block", "cells_per_lane")}, "diagnostics": diag}
+            "launch": {k: cfg[k] for k in ("block", "cells_per_lane")}, "diagnostics": diag,
+            "runs_ms_per_step": [round(c, 4) for c in chunks],
+            "runs_median_ms": round(float(np.median(chunks)), 4) if chunks else None,
+            "runs_spread": round((max(chunks) - min(chunks)) / float(np.median(chunks)), 4) if chunks else None}
 
 
 def periodic_box(steps=50, warmup=5):
