@@ -105,3 +105,26 @@ def test_fused_step_refuses_ensembles(env):
         with pytest.raises(lbm.LbmError) as ei:
             g.step_diagnostics()
         assert ei.value.code == -4
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (5, 3, 2), (70, 2, 3)])
+@pytest.mark.parametrize("storage", ["fp32", "fp16s", "p16_1s"])
+def test_fused_step_on_tiny_and_ragged_lattices(env, storage, dims):
+    """Lattices smaller than a wavefront, and a row of 70 cells (one full and
+    one nearly empty wavefront): the lanes past the row's end take part in
+    the reduction without adding to it or storing."""
+    torch, lbm, orc = env
+    nx, ny, nz = dims
+    (a, b), u, N = _pair(lbm, orc, storage, 19, "trt", nx=nx, ny=ny, nz=nz, seed=11)
+    try:
+        da = a.diagnostics(0)
+        a.step(1)
+        db = b.step_diagnostics()
+        for k in FIELDS:
+            assert da[k] == db[k], (k, da[k], db[k])
+        assert np.array_equal(da["momentum"], db["momentum"])
+        assert np.array_equal(da["force_on_solid"], db["force_on_solid"])
+        assert np.array_equal(a.get_ddf(0), b.get_ddf(0))
+    finally:
+        a.close()
+        b.close()
