@@ -313,6 +313,30 @@ def karman(storages=("fp16s", "fp16c", "fp32"), steps=50, warmup=10):
                         "tau 0.532 (Re 150)", "steps_from_start": steps + warmup + 2, "rows": rows}
 
 
+def placement(n=512, handles=5, steps=50, warmup=10):
+    """The headline step (512 threads, one cell per lane) on fresh handles
+    whose buffers land in different places: before handle k the allocator's
+    cache is emptied and a spacer of k (64 MiB + 4 KiB) is taken and held, so
+    every handle's DDF buffers start at a different address and on different
+    physical pages.  ms per step of each (events, as the headline)."""
+    import torch
+    times, spacers = [], []
+    for k in range(handles):
+        torch.cuda.empty_cache()
+        spacers.append(torch.empty(k * ((64 << 20) + 4096) + 4096, dtype=torch.uint8, device="cuda"))
+        g, _ = cavity(n, HEADLINE)
+        try:
+            g.set_launch(mode=0, block=512, cells_per_lane=1)
+            times.append(time_steps(g, steps, warmup))
+        finally:
+            g.close()
+    del spacers
+    torch.cuda.empty_cache()
+    med = float(np.median(times))
+    return {"handles": handles, "steps": steps, "ms_per_step": [round(t, 4) for t in times],
+            "spread": round((max(times) - min(times)) / med, 4)}
+
+
 def memory_bandwidths(nbytes=4 << 30, reps=10):
     """Achievable HBM bandwidth of the library's memory microbenchmarks (the
     paper's appendix memory benchmarks): a plain copy (bytes read + bytes
@@ -413,6 +437,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 256-lattice ensembles")
     ap.add_argument("--no-karman", action="store_true", help="skip the full-size Karman channel (D3Q27)")
+    ap.add_argument("--placement", type=int, default=0,
+                    help="also time the headline step on this many fresh handles placed apart")
     ap.add_argument("--no-periodic", action="store_true",
                     help="skip the periodic-box runs (the paper's performance workload, other velocity sets)")
     args = ap.parse_args()
@@ -456,6 +482,10 @@ def main():
     if not args.no_periodic:
         print("[bench] periodic boxes", file=sys.stderr, flush=True)
         per = periodic_box()
+    place = None
+    if args.placement > 0:
+        print(f"[bench] placement: {args.placement} fresh handles", file=sys.stderr, flush=True)
+        place = placement(args.n, args.placement)
     cpu = None
     if not args.no_cpu:
         print("[bench] CPU reference timing", file=sys.stderr, flush=True)
@@ -491,6 +521,7 @@ def main():
         "ensemble": ens,
         "karman": kar,
         "periodic_box": per,
+        "placement": place,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(line), flush=True)
