@@ -63,6 +63,13 @@ int main(void) {
     lbm_diag d;
     CHECK(lbm_diagnostics(h, 0, NULL, &d));
     CHECK(lbm_get_rho_u(h, 0, rho, u));
+    /* one more step that also reduces the state it reads: the same sums */
+    lbm_diag d2;
+    CHECK(lbm_step_diagnostics(h, NULL, &d2));
+    const int fused_same = d2.mass == d.mass && d2.kinetic_energy == d.kinetic_energy && d2.u_max == d.u_max &&
+                           d2.momentum[0] == d.momentum[0] && d2.momentum[1] == d.momentum[1] &&
+                           d2.momentum[2] == d.momentum[2] && d2.force_on_solid[1] == d.force_on_solid[1] &&
+                           d2.step == d.step;
     lbm_info info;
     CHECK(lbm_info_get(h, &info));
     if (lbm_set_boundaries(h, 1, flags) != LBM_EINVAL) return 2;      /* one lattice only */
@@ -76,9 +83,9 @@ int main(void) {
             py += rho[c] * u[N + c];
         }
     printf("c_caller fluid=%zu steps=%lld mass=%.12e host_mass=%.12e momentum_y=%.12e host_momentum_y=%.12e "
-           "u_max=%.6e nonfinite=%lld device_bytes=%lld\n",
+           "u_max=%.6e nonfinite=%lld device_bytes=%lld fused_same=%d steps_after=%lld\n",
            fluid, (long long)d.step, d.mass, mass, d.momentum[1], py, d.u_max, (long long)d.nonfinite_cells,
-           (long long)info.device_bytes);
+           (long long)info.device_bytes, fused_same, (long long)info.step);
     free(flags);
     free(rho);
     free(u);

@@ -43,3 +43,4 @@ def test_c_caller_runs(tmp_path):
     assert abs(v["momentum_y"] - v["host_momentum_y"]) <= 1e-9 * v["fluid"]
     assert abs(v["mass"] / v["fluid"] - 1) < 1e-4
     assert 1e-3 < v["u_max"] < 0.05
+    assert v["fused_same"] == 1 and v["steps_after"] == 301      # lbm_step_diagnostics: same sums, one more step
