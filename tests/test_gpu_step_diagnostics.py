@@ -30,7 +30,7 @@ def env():
 
 def _pair(lbm, orc, storage, q, collision, nx=600, ny=40, nz=30, seed=3):
     N = nx * ny * nz
-    flags, rho, u = one_step_inputs(nx, ny, nz, q, seed=seed + q)
+    flags, rho, u = one_step_inputs(nx, ny, nz, q, seed=seed + q, with_moving=nz > 1)
     force, wall_u, eq_u = (2e-5, -1e-5, 0.0), (0.0, 0.07, 0.02), (0.03, 0.0, 0.0)
     eq = (flags & wl.EQ) != 0
     rho[eq] = 1.01
@@ -72,6 +72,27 @@ def test_fused_step_matches_diagnostics_then_step(env, storage, q, collision):
         # and the handles stay in step afterwards (the fused call flipped the buffers)
         a.step(5)
         b.step(5)
+        assert np.array_equal(a.get_ddf(0), b.get_ddf(0))
+    finally:
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("q,collision,dims", [(9, "srt", (600, 40, 1)), (15, "trt", (600, 20, 12))])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16s", "fp16c", "p16_2c"])
+def test_fused_step_other_velocity_sets(env, storage, q, collision, dims):
+    """D2Q9 (one z-plane, no lid) and D3Q15: the same bit-identities."""
+    torch, lbm, orc = env
+    say("step_diagnostics", storage, q, collision, dims)
+    (a, b), u, N = _pair(lbm, orc, storage, q, collision, *dims)
+    try:
+        da = a.diagnostics(0)
+        a.step(1)
+        db = b.step_diagnostics()
+        for k in FIELDS:
+            assert da[k] == db[k], (k, da[k], db[k])
+        assert np.array_equal(da["momentum"], db["momentum"])
+        assert np.array_equal(da["force_on_solid"], db["force_on_solid"])
         assert np.array_equal(a.get_ddf(0), b.get_ddf(0))
     finally:
         a.close()
