@@ -157,36 +157,39 @@ __host__ __device__ __forceinline__ float posit_s_decode(uint32_t c) {
     return posit_s_decode_sext<ES>((int32_t)(int16_t)(uint16_t)c);
 }
 
+// The same for codes whose regime is a run of zeros (bit 14 of the code
+// clear, values below 2^-7 in magnitude): there the value is linear in the
+// magnitude m.  With es = 0, m = 2^(14-k) (1 + f / 2^(14-k)) for a run of k
+// zeros and the value 2^(-k-7) (1 + f / 2^(14-k)) = m 2^-21; with es = 1 the
+// float of m has exponent field 141 - k and e at the top of its mantissa, so
+// its bits shifted left by one carry (2 (141 - k) + e) in the exponent field,
+// from which 162 is taken to reach 120 - 2k + e.  Code 0 (0.0) gives garbage
+// that the minimum with the float's own bits (0) removes, as for P16_2C.
+template <int ES>
+__host__ __device__ __forceinline__ float posit_s_decode_zeros_run(int32_t cs) {
+    const uint32_t mag = (uint32_t)cs & 0x3FFFu;
+    const uint32_t b = f2u((float)mag);                    // exact: mag < 2^14
+    const uint32_t bits = ES == 0 ? umin(b - (21u << 23), b) : umin((b << 1) - (162u << 23), b);
+    return u2f(bits | ((uint32_t)cs & 0x80000000u));
+}
+
 // Asymmetric P16_2C: r leading zeros close with a one (no regime sign), then
 // 2 exponent bits and 12 - r mantissa bits; value 2^(-3-4r+e)(1 + m/2^(12-r)).
-// Shifting the regime and its closing one out of the top leaves the exponent
-// bits at 31..30 and the mantissa below; the FP32 exponent field is then
-// 124 - 4r = 4 (31 - r) plus e.  Device: one fixed sequence as above (r is
-// one v_ffbh_u32).
+// The 15-bit magnitude converted to float does the regime count: its leading
+// one is at bit 14 - r, so the float's exponent field is 141 - r and its
+// mantissa holds e at the top, then m.  Shifting the float's bits left by 2
+// multiplies the exponent field by 4 and moves e into its low bits, leaving
+// m in place of the mantissa: (4 (141 - r) + e) mod 512 at bits 31..23, from
+// which 440 is taken to reach 124 - 4r + e (68 .. 127 for every code, so the
+// modular arithmetic ends in range).  Code 0 converts to 0.0, whose shifted
+// bits give garbage: the minimum with the float's own bits (0 there, and
+// above every result for any other code, which converts to 1.0 or more)
+// maps it to 0.  Five instructions with the sign.
 __host__ __device__ __forceinline__ float p162c_decode_sext(int32_t cs) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    uint32_t out, t, r, rest, e;
-    asm("v_lshlrev_b32 %1, 17, %5\n\t"
-        "v_cmp_ne_u32 vcc, 0, %1\n\t"
-        "v_ffbh_u32 %2, %1\n\t"
-        "v_lshlrev_b32 %3, %2, %1\n\t"
-        "v_bfe_u32 %3, %3, 6, 25\n\t"
-        "v_sub_u32 %4, 31, %2\n\t"
-        "v_lshl_add_u32 %3, %4, 25, %3\n\t"
-        "v_cndmask_b32 %3, 0, %3, vcc\n\t"
-        "v_and_or_b32 %0, %5, %6, %3"
-        : "=v"(out), "=&v"(t), "=&v"(r), "=&v"(rest), "=&v"(e)
-        : "v"(cs), "s"(0x80000000u)
-        : "vcc");
-    return u2f(out);
-#else
-    const uint32_t t = (uint32_t)cs << 17;
-    const int r = __builtin_clz(t | 1u);
-    const uint32_t rest = ((t << r) << 1) >> 7;          // exponent bits at 24..23, mantissa below
-    uint32_t bits = ((uint32_t)(31 - r) << 25) + rest;
-    bits = t ? bits : 0u;
+    const uint32_t mag = (uint32_t)cs & 0x7FFFu;
+    const uint32_t b = f2u((float)mag);                    // exact: mag < 2^15
+    const uint32_t bits = umin((b << 2) - (440u << 23), b);
     return u2f(bits | ((uint32_t)cs & 0x80000000u));
-#endif
 }
 __host__ __device__ __forceinline__ float p162c_decode(uint32_t c) {
     return p162c_decode_sext((int32_t)(int16_t)(uint16_t)c);
@@ -271,6 +274,22 @@ struct RawCodec {
     }
     template <class A> __device__ __forceinline__ static auto store_raw(A v, const EncEntry* t) {
         return Codec<F>::template store<A>(v, t);
+    }
+};
+
+// Formats with a cheaper decoder for the codes whose regime is a run of
+// zeros (bit 14 clear): the sign-magnitude posits P16_0S and P16_1S.
+template <int F> struct ZerosRun { static constexpr bool value = false; };
+template <> struct ZerosRun<S_P16_0S> {
+    static constexpr bool value = true;
+    template <class A> __device__ __forceinline__ static A load(uint16_t v) {
+        return posit_s_decode_zeros_run<0>((int16_t)v);
+    }
+};
+template <> struct ZerosRun<S_P16_1S> {
+    static constexpr bool value = true;
+    template <class A> __device__ __forceinline__ static A load(uint16_t v) {
+        return posit_s_decode_zeros_run<1>((int16_t)v);
     }
 };
 

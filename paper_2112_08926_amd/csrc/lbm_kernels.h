@@ -219,22 +219,47 @@ __device__ __forceinline__ bool wave_has_walls(const LatDev& L, uint32_t n_first
 // same load instruction (chosen per lane from the cell's wall mask), so a
 // wavefront next to a wall issues one extra load (the mask), not one per
 // bounced direction.
+// Decodes the Q pulled codes; for the sign-magnitude posits, with the
+// cheaper decoder when no code of the wavefront has a run of ones as regime
+// (a wavefront-uniform choice: values below 2^-7 everywhere, as in most of a
+// flow's cells), else with the full one.
+template <int Q, int F, class A, bool RAW>
+__device__ __forceinline__ void decode_pulled(const typename Codec<F>::T (&c)[Q], A (&f)[Q]) {
+    if constexpr (ZerosRun<F>::value) {
+        uint32_t any = 0;
+#pragma unroll
+        for (int i = 0; i < Q; i++) any |= (uint32_t)c[i];
+        if (__any((any & 0x4000u) != 0)) {
+#pragma unroll
+            for (int i = 0; i < Q; i++) f[i] = load_ddf<Q, F, A, RAW>(c[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; i++) f[i] = ZerosRun<F>::template load<A>(c[i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) f[i] = load_ddf<Q, F, A, RAW>(c[i]);
+    }
+}
+
 template <int Q, int F, class A, bool RAW, bool LANE_ROWS = false>
 __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
                                      const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp,
                                      uint32_t n, bool walls, A (&f)[Q]) {
     using T = typename Codec<F>::T;
     const size_t plane = L.plane;
+    T c[Q];
     if (!walls) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             if constexpr (LANE_ROWS) {
-                f[i] = load_ddf<Q, F, A, RAW>(ld_off(src + (size_t)i * plane, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp)));
+                c[i] = ld_off(src + (size_t)i * plane, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
             } else {
                 const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
-                f[i] = load_ddf<Q, F, A, RAW>(ld_off(p, src_x<Q>(i, x, xm, xp)));
+                c[i] = ld_off(p, src_x<Q>(i, x, xm, xp));
             }
         }
+        decode_pulled<Q, F, A, RAW>(c, f);
         return;
     }
     const uint32_t m = ld_mask(L.wall_mask, n);
@@ -256,8 +281,9 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
             p = wall ? src + (size_t)opp(i) * plane : p;
             idx = wall ? n : idx;
         }
-        f[i] = load_ddf<Q, F, A, RAW>(ld_off(p, idx));
+        c[i] = ld_off(p, idx);
     }
+    decode_pulled<Q, F, A, RAW>(c, f);
     // ... then the moving walls' momentum, only in wavefronts next to one.
     if (__any((m & 0x80000000u) != 0)) {
 #pragma unroll

@@ -15,6 +15,19 @@ int main(int argc, char** argv) {
     const int fmt = std::atoi(argv[1]);
     std::vector<float> dec(65536);
     for (uint32_t c = 0; c < 65536; c++) dec[c] = lbm::decode16(fmt, c);
+    // the sign-magnitude posits' shortcut for codes with a run of zeros as
+    // regime (bit 14 clear) must equal the full decoder there, bit for bit
+    if (fmt == lbm::S_P16_0S || fmt == lbm::S_P16_1S)
+        for (uint32_t c = 0; c < 65536; c++) {
+            if (c & 0x4000u) continue;
+            const int32_t cs = (int32_t)(int16_t)(uint16_t)c;
+            const float z = fmt == lbm::S_P16_0S ? lbm::posit_s_decode_zeros_run<0>(cs)
+                                                 : lbm::posit_s_decode_zeros_run<1>(cs);
+            if (lbm::f2u(z) != lbm::f2u(dec[c])) {
+                std::fprintf(stderr, "zeros-run shortcut differs at code 0x%04x\n", c);
+                return 8;
+            }
+        }
     FILE* f = std::fopen(argv[2], "wb");
     if (!f || std::fwrite(dec.data(), 4, dec.size(), f) != dec.size()) return 3;
     std::fclose(f);
