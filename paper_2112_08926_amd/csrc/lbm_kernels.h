@@ -1216,11 +1216,13 @@ __global__ void __launch_bounds__(256) k_moments(LatDev L, int parity, double* _
 // Sum (or max) of a double over each row of 16 lanes with DPP moves (no LDS):
 // xor 1 and xor 2 inside quads, then the mirrored half rows and rows; every
 // lane of a row ends with the row's result, combined in a fixed order.
+// dpp_f64: a permutation inside each row (every lane is written, from a lane
+// that exists), so the destination needs no initial value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
 }
 template <int CTRL, int ROWS>
@@ -1284,13 +1286,17 @@ __device__ __forceinline__ double reduce4(double f0, double f1, double f2, doubl
 // non-negative values) in a fixed order, without a barrier at the end: each
 // wavefront reduces its values -- the sums four fields at a time, one field
 // per row of 16 lanes after two cross-lane swaps (reduce4), the max with DPP
-// -- and puts them in its LDS slot (the wall force only in wavefronts next
+// -- and puts them in its LDS slots (the wall force only in wavefronts next
 // to a wall, bit 7 of the wavefront-uniform `skip`; 0 otherwise), then counts
 // itself in; the wavefront that counts last sums the slots in wavefront
-// order (lane k field k) and writes out[k].  The others leave as soon as they
-// have counted, instead of waiting for the slowest.  `count` must be zero at
-// entry for the whole workgroup (set before a barrier at the start of the
-// kernel).
+// order and writes out[k].  The others leave as soon as they have counted,
+// instead of waiting for the slowest.  `count` must be zero at entry for the
+// whole workgroup (set before a barrier at the start of the kernel).
+// Slots: reduce4 leaves its fields in the rows in the order f0, f2, f1, f3,
+// so each group is passed in the order that puts field g_r in row r, and row
+// r of group g writes slot 4 g + r: fields 0-3, then 4, 5, 6, 10, then 7, 8,
+// 9, and the max in slot 11.  Which argument a field is passed as does not
+// change its sum: every field goes through the same tree of additions.
 __device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], uint32_t skip, double* out,
                                                    uint32_t* count) {
     constexpr int kMaxWaves = 1024 / 64;
@@ -1298,16 +1304,15 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], u
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
     const int row = lane >> 4;
     const bool last_of_row = (lane & 15) == 15;
-    // rows of reduce4's result: f0, f2, f1, f3
-    const double g1 = reduce4(acc[0], acc[1], acc[2], acc[3]);
-    const double g2 = reduce4(acc[4], acc[10], acc[5], acc[6]);
+    const double g1 = reduce4(acc[0], acc[2], acc[1], acc[3]);
+    const double g2 = reduce4(acc[4], acc[6], acc[5], acc[10]);
     if (last_of_row) {
-        s[row == 0 ? 0 : row == 1 ? 2 : row == 2 ? 1 : 3][wave] = g1;
-        s[row == 0 ? 4 : row == 1 ? 5 : row == 2 ? 10 : 6][wave] = g2;
+        s[row][wave] = g1;
+        s[4 + row][wave] = g2;
     }
     double g3 = 0.0;
-    if (!((skip >> 7) & 1u)) g3 = reduce4(acc[7], acc[8], acc[9], 0.0);
-    if (last_of_row && row != 3) s[row == 0 ? 7 : row == 1 ? 9 : 8][wave] = g3;
+    if (!((skip >> 7) & 1u)) g3 = reduce4(acc[7], acc[9], acc[8], 0.0);
+    if (last_of_row && row != 3) s[8 + row][wave] = g3;
     const double mx = wave_reduce<true>(acc[kDiagFields - 1]);
     if (lane == 63) s[kDiagFields - 1][wave] = mx;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1319,7 +1324,8 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], u
         if (lane < kDiagFields) {
             double v = s[lane][0];
             for (int w = 1; w < nwaves; w++) v = (lane == kDiagFields - 1) ? fmax(v, s[lane][w]) : v + s[lane][w];
-            out[lane] = v;
+            const int field = lane == 7 ? 10 : (lane >= 8 && lane <= 10 ? lane - 1 : lane);
+            out[field] = v;
         }
     }
 }
