@@ -146,6 +146,16 @@ def diag_cost(g, flags, q, storage, every, steps):
                      "nonfinite_updates": d["nonfinite_updates"]}}
 
 
+LAUNCH_KINDS = {0: "row tiles", 1: "batched row tiles", 2: "cell-contiguous tiles"}
+
+
+def launch_desc(cfg):
+    """The autotuned launch: its kind (include/lbm.h lbm_launch_mode),
+    workgroup size and cells per lane."""
+    return {"kind": LAUNCH_KINDS.get(cfg["mode"], str(cfg["mode"])), "block": cfg["block"],
+            "cells_per_lane": cfg["cells_per_lane"]}
+
+
 def measure_format(storage, n, steps, warmup, diag_every=0):
     g, flags = cavity(n, storage)
     try:
@@ -167,7 +177,7 @@ def measure_format(storage, n, steps, warmup, diag_every=0):
             "achieved_GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS,
             "kinetic_energy": d["kinetic_energy"], "nonfinite": d["nonfinite_cells"],
             "nonfinite_updates": d["nonfinite_updates"],
-            "launch": {k: cfg[k] for k in ("block", "cells_per_lane")}, "diagnostics": diag,
+            "launch": launch_desc(cfg), "diagnostics": diag,
             "runs_ms_per_step": [round(c, 4) for c in chunks],
             "runs_median_ms": round(float(np.median(chunks)), 4) if chunks else None,
             "runs_spread": round((max(chunks) - min(chunks)) / float(np.median(chunks)), 4) if chunks else None}
@@ -306,7 +316,7 @@ def karman(storages=("fp16s", "fp16c", "fp32"), steps=50, warmup=10):
                      "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4),
                      "force_on_cylinder": [float(v) for v in d["force_on_solid"]],
                      "nonfinite": d["nonfinite_cells"], "drag_every_10": diag,
-                     "launch": {k: cfg[k] for k in ("block", "cells_per_lane")}})
+                     "launch": launch_desc(cfg)})
         print(f"[bench] karman D3Q27 {storage}: {rows[-1]['mlups']:.0f} MLUPs/s, {gbs:.0f} GB/s",
               file=sys.stderr, flush=True)
     return {"workload": "Karman channel 1024x256x64, D3Q27 TRT, cylinder R 16, EQ inflow/outflow u 0.05, "
