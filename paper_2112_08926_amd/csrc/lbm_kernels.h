@@ -300,6 +300,59 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
     }
 }
 
+// The pull's parts for the diagnostics kernels, which also need the wall
+// mask and the bounced directions' values before the moving walls' term
+// (those are this cell's own opposite DDFs, which the momentum exchange
+// reads).  The same loads, decode (decode_pulled) and wall terms as pull,
+// which keeps them in one body for the step kernels.
+// pull_codes: the Q loads; m = the cell's wall mask in a wavefront with
+// walls (a wall source hands back this cell's own opposite DDF, taken by the
+// same load instruction with a per-lane address), else 0.
+template <int Q, int F>
+__device__ __forceinline__ void pull_codes(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
+                                           const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp, uint32_t n,
+                                           bool walls, typename Codec<F>::T (&c)[Q], uint32_t& m) {
+    using T = typename Codec<F>::T;
+    const size_t plane = L.plane;
+    if (!walls) {
+        m = 0;
+#pragma unroll
+        for (int i = 0; i < Q; i++) c[i] = ld_off(src + ((size_t)i * plane + src_row<Q>(rc, i)), src_x<Q>(i, x, xm, xp));
+        return;
+    }
+    m = ld_mask(L.wall_mask, n);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
+        uint32_t idx = src_x<Q>(i, x, xm, xp);
+        if (i > 0) {
+            const bool wall = (m >> i) & 1u;
+            p = wall ? src + (size_t)opp(i) * plane : p;
+            idx = wall ? n : idx;
+        }
+        c[i] = ld_off(p, idx);
+    }
+}
+// add_moving_walls: to the decoded values (RAW: the step's raw units), the
+// moving walls' momentum, only in wavefronts next to one.
+template <int Q, int F, class A, bool RAW>
+__device__ __forceinline__ void add_moving_walls(const LatDev& L, const RowCtx& rc, uint32_t x, uint32_t xm,
+                                                 uint32_t xp, uint32_t m, A (&f)[Q]) {
+    if (__any((m & 0x80000000u) != 0)) {
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (((m >> i) & 1u) && (m & 0x80000000u)) {
+                const uint8_t fs = ld_off(L.flags, src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp));
+                if (fs & F_MOVING) {
+                    const A cu = (A)(VelSet<Q>::c[i][0] * L.wall_u[0] + VelSet<Q>::c[i][1] * L.wall_u[1] +
+                                     VelSet<Q>::c[i][2] * L.wall_u[2]);
+                    f[i] += (A)(6.0 * VelSet<Q>::w(i) * kRawScale<F, RAW>) * cu;
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ fields
 // Momentum by alternating pair sums (Sec. 2.2), in index order.
 template <int Q, class A>
@@ -1332,15 +1385,14 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kDiagFields], u
 
 // The FP64 contributions of one fluid cell (flags fl) whose pulled DDFs are
 // f, added to v: mass, momentum, kinetic energy, the error norms against
-// u_ref, the momentum exchange into walls, the non-finite count and the
-// largest |u|^2.  The moments are those the next step sees after streaming
+// u_ref, the non-finite count and the largest |u|^2 (the momentum exchange
+// into walls is diag_exchange's, taken from f before the moving walls' term).  The moments are those the next step sees after streaming
 // (velocity with F/2, not clamped), in the step's arithmetic.  RAWE: f in
 // units of 2^-RAWE (the step's raw units); the sums are taken in those units
 // and scaled back, a power of two, so rho and j are bit-identical to sums of
 // the unscaled values.
 template <int Q, int F, class A, int RAWE = 0>
-__device__ __forceinline__ void diag_cell(const LatDev& L, const typename Codec<F>::T* __restrict__ src, uint32_t fl,
-                                          uint32_t x, uint32_t y, uint32_t z, uint32_t n, const A (&f)[Q],
+__device__ __forceinline__ void diag_cell(const LatDev& L, uint32_t fl, uint32_t n, const A (&f)[Q],
                                           const double* __restrict__ u_ref, double (&v)[kDiagFields]) {
     if (fl & (F_SOLID | F_EQ)) return;
     A rho, j[3];
@@ -1359,6 +1411,7 @@ __device__ __forceinline__ void diag_cell(const LatDev& L, const typename Codec<
     const double r = (double)rho, ux = (double)(j[0] * inv), uy = (double)(j[1] * inv), uz = (double)(j[2] * inv);
     if (!(isfinite(r) && isfinite(ux) && isfinite(uy) && isfinite(uz))) {
         v[10] += 1.0;
+        v[7] = v[8] = v[9] = 0.0;                                // no wall force from such a cell
         return;
     }
     v[0] += r;
@@ -1374,24 +1427,30 @@ __device__ __forceinline__ void diag_cell(const LatDev& L, const typename Codec<
         v[5] += (ux - rx) * (ux - rx) + (uy - ry) * (uy - ry) + (uz - rz) * (uz - rz);
         v[6] += rx * rx + ry * ry + rz * rz;
     }
-    if (fl & F_NEAR) {
-        // momentum exchange: every link to a wall source x - c_i carries
-        // c_opp (2 (f*_opp + w_opp) + 6 w_i c_i.u_w) into the wall, f*_opp
-        // being what this cell sent towards the wall in the last step.  A
-        // loop, not unrolled (few cells take it); the source cell is found
-        // from the direction's components, so no array of the row context is
-        // indexed at run time (that would put it in scratch memory).
-        const size_t plane = L.plane;
-        const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
-        const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
-        const uint32_t m = ld_mask(L.wall_mask, n);
-#pragma unroll 1
-        for (int i = 1; i < Q; i++) {
-            if (!((m >> i) & 1u)) continue;
+}
+
+// The momentum exchange of one fluid cell next to a wall (wall mask m) into
+// v[7..9], which hold 0 for this cell on entry: every link to a wall source
+// x - c_i carries c_opp (2 (f*_opp + w_opp) + 6 w_i c_i.u_w) into the wall,
+// f*_opp being what this cell sent towards the wall in the last step, which
+// the pull took for direction i (this cell's own opposite DDF): f[i] before
+// the moving walls' term, in units of 2^-RAWE (scaled back exactly), so no
+// load waits here.  A branch per direction, skipped by wavefronts in which
+// no lane has that wall source; only a moving wall source needs a load (its
+// flag).  diag_cell clears v[7..9] again for a cell whose moments are not
+// finite.
+template <int Q, int F, class A, int RAWE = 0>
+__device__ __forceinline__ void diag_exchange(const LatDev& L, uint32_t x, uint32_t y, uint32_t z, uint32_t m,
+                                              const A (&f)[Q], double (&v)[kDiagFields]) {
+    constexpr A kUnraw = (A)(1.0 / exp2i(RAWE));
+    const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
+    const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        if ((m >> i) & 1u) {
             const int o = opp(i);
             const int cx = VelSet<Q>::c[i][0], cy = VelSet<Q>::c[i][1], cz = VelSet<Q>::c[i][2];
-            const double fo = (double)load_ddf<Q, F, A, false>(ld_off(src + (size_t)o * plane, n)) +
-                              VelSet<Q>::w(o) * L.shift;
+            const double fo = (double)(f[i] * kUnraw) + VelSet<Q>::w(o) * L.shift;
             double mv = 0.0;
             if (m & 0x80000000u) {
                 const uint32_t sx = cx > 0 ? xm : (cx < 0 ? xp : x);
@@ -1399,10 +1458,13 @@ __device__ __forceinline__ void diag_cell(const LatDev& L, const typename Codec<
                 const uint8_t fs = ld_off(L.flags, sx + (sy + sz * L.ny) * L.nx);
                 if (fs & F_MOVING) mv = 6.0 * VelSet<Q>::w(i) * (cx * L.wall_u[0] + cy * L.wall_u[1] + cz * L.wall_u[2]);
             }
-            const double t = 2.0 * fo + mv;                         // c_opp = -c_i
-            v[7] -= cx * t;
-            v[8] -= cy * t;
-            v[9] -= cz * t;
+            const double t = 2.0 * fo + mv;                             // c_opp = -c_i
+            // a component 0 adds nothing: the sums start at +0, and a
+            // non-finite t comes with non-finite moments, whose force diag_cell
+            // clears
+            if (cx) v[7] -= cx * t;
+            if (cy) v[8] -= cy * t;
+            if (cz) v[9] -= cz * t;
         }
     }
 }
@@ -1440,9 +1502,14 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(LatDev L, int parity, con
         const uint8_t fl = ld_off(L.flags, n);
         const uint32_t xm = x == 0 ? L.nx - 1 : x - 1;
         const uint32_t xp = x + 1 == L.nx ? 0 : x + 1;
+        T c[Q];
+        uint32_t m;
         A f[Q];
-        pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);   // the step's raw units
-        diag_cell<Q, F, A, Codec<F>::kRawExp>(L, src, fl, x, y, z, n, f, u_ref, v);
+        pull_codes<Q, F>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), c, m);
+        decode_pulled<Q, F, A, true>(c, f);                                  // the step's raw units
+        if ((fl & (F_SOLID | F_EQ | F_NEAR)) == F_NEAR) diag_exchange<Q, F, A, Codec<F>::kRawExp>(L, x, y, z, m, f, v);
+        add_moving_walls<Q, F, A, true>(L, rc, x, xm, xp, m, f);
+        diag_cell<Q, F, A, Codec<F>::kRawExp>(L, fl, n, f, u_ref, v);
     }
     // the wall force is reduced only by wavefronts next to a wall
     const uint32_t skip = __any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0) ? 0u : (1u << 7);
@@ -1484,13 +1551,19 @@ __global__ void __launch_bounds__(kDiagThreads) k_step_diag(LatDev L, int parity
 
     A f[Q], fo[Q];
     const bool special = (fl & (F_SOLID | F_EQ)) != 0;
-    pull<Q, F, A, true>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), f);
     {
         // the diagnostics first, so that their registers are free for the collision
         double v[kDiagFields];
 #pragma unroll
         for (int k = 0; k < kDiagFields; k++) v[k] = 0.0;
-        if (active) diag_cell<Q, F, A, Codec<F>::kRawExp>(L, src, fl, x, y, z, n, f, u_ref, v);
+        T cin[Q];
+        uint32_t m;
+        pull_codes<Q, F>(L, src, rc, x, xm, xp, n, wave_has_walls(L, n), cin, m);
+        decode_pulled<Q, F, A, true>(cin, f);
+        if (active && (fl & (F_SOLID | F_EQ | F_NEAR)) == F_NEAR)
+            diag_exchange<Q, F, A, Codec<F>::kRawExp>(L, x, y, z, m, f, v);
+        add_moving_walls<Q, F, A, true>(L, rc, x, xm, xp, m, f);
+        if (active) diag_cell<Q, F, A, Codec<F>::kRawExp>(L, fl, n, f, u_ref, v);
         const uint32_t skip = __any(v[7] != 0.0 || v[8] != 0.0 || v[9] != 0.0) ? 0u : (1u << 7);
         block_reduce_store(v, skip, partials + ((size_t)(z * L.ny + y) * segs + seg) * kDiagFields, &waves_done);
     }
