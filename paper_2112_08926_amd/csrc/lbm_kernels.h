@@ -242,57 +242,6 @@ __device__ __forceinline__ void decode_pulled(const typename Codec<F>::T (&c)[Q]
     }
 }
 
-// The Q loads of a cell in a wavefront next to a wall (m: the cell's wall
-// mask; a wall source hands back this cell's own opposite DDF, taken by the
-// same load instruction with a per-lane address).  Where two planes fit in
-// 32-bit byte offsets, each load takes one scalar base: the lower plane of
-// the direction's opposite pair (directions 2k-1 and 2k are opposite) at the
-// lower of the source row and this cell's row (n = own + x), plus a per-lane
-// offset, the source cell's or, from a wall, this cell's in the opposite
-// plane; both stay below two planes.  Else (and for per-lane rows) 64-bit
-// addresses per lane.
-template <int Q, int F, bool LANE_ROWS>
-__device__ __forceinline__ void pull_wall_codes(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
-                                                const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp, uint32_t n,
-                                                uint32_t m, typename Codec<F>::T (&c)[Q]) {
-    using T = typename Codec<F>::T;
-    const size_t plane = L.plane;
-    bool pairs = false;
-    if constexpr (!LANE_ROWS) pairs = (uint64_t)plane * (2 * sizeof(T)) < (1ull << 32);
-    if (pairs) {
-        const uint32_t own = rc.rows[4];
-        c[0] = ld_off(src + own, x);
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            const int lo = (i & 1) ? i : i - 1;
-            const uint32_t ri = src_row<Q>(rc, i);
-            const uint32_t r0 = ri < own ? ri : own;
-            const uint32_t normal = ((i & 1) ? 0u : (uint32_t)plane) + (ri - r0) + src_x<Q>(i, x, xm, xp);
-            const uint32_t bounce = ((i & 1) ? (uint32_t)plane : 0u) + (own - r0) + x;
-            c[i] = ld_off(src + ((size_t)lo * plane + r0), ((m >> i) & 1u) ? bounce : normal);
-        }
-        return;
-    }
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        const T* p;
-        uint32_t idx;
-        if constexpr (LANE_ROWS) {
-            p = src + (size_t)i * plane;
-            idx = src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp);
-        } else {
-            p = src + ((size_t)i * plane + src_row<Q>(rc, i));
-            idx = src_x<Q>(i, x, xm, xp);
-        }
-        if (i > 0) {
-            const bool wall = (m >> i) & 1u;
-            p = wall ? src + (size_t)opp(i) * plane : p;
-            idx = wall ? n : idx;
-        }
-        c[i] = ld_off(p, idx);
-    }
-}
-
 template <int Q, int F, class A, bool RAW, bool LANE_ROWS = false>
 __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T* __restrict__ src,
                                      const RowCtx& rc, uint32_t x, uint32_t xm, uint32_t xp,
@@ -316,7 +265,24 @@ __device__ __forceinline__ void pull(const LatDev& L, const typename Codec<F>::T
     const uint32_t m = ld_mask(L.wall_mask, n);
     // All Q loads first, addresses chosen by selects (no branch between the
     // loads, so they are all in flight at once) ...
-    pull_wall_codes<Q, F, LANE_ROWS>(L, src, rc, x, xm, xp, n, m, c);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const T* p;
+        uint32_t idx;
+        if constexpr (LANE_ROWS) {
+            p = src + (size_t)i * plane;
+            idx = src_row<Q>(rc, i) + src_x<Q>(i, x, xm, xp);
+        } else {
+            p = src + ((size_t)i * plane + src_row<Q>(rc, i));
+            idx = src_x<Q>(i, x, xm, xp);
+        }
+        if (i > 0) {
+            const bool wall = (m >> i) & 1u;
+            p = wall ? src + (size_t)opp(i) * plane : p;
+            idx = wall ? n : idx;
+        }
+        c[i] = ld_off(p, idx);
+    }
     decode_pulled<Q, F, A, RAW>(c, f);
     // ... then the moving walls' momentum, only in wavefronts next to one.
     if (__any((m & 0x80000000u) != 0)) {
@@ -355,7 +321,17 @@ __device__ __forceinline__ void pull_codes(const LatDev& L, const typename Codec
         return;
     }
     m = ld_mask(L.wall_mask, n);
-    pull_wall_codes<Q, F, false>(L, src, rc, x, xm, xp, n, m, c);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
+        uint32_t idx = src_x<Q>(i, x, xm, xp);
+        if (i > 0) {
+            const bool wall = (m >> i) & 1u;
+            p = wall ? src + (size_t)opp(i) * plane : p;
+            idx = wall ? n : idx;
+        }
+        c[i] = ld_off(p, idx);
+    }
 }
 // add_moving_walls: to the decoded values (RAW: the step's raw units), the
 // moving walls' momentum, only in wavefronts next to one.
