@@ -173,6 +173,26 @@ __host__ __device__ __forceinline__ float posit_s_decode_zeros_run(int32_t cs) {
     return u2f(bits | ((uint32_t)cs & 0x80000000u));
 }
 
+// P16_0S encoder for |x| < 2^-7, where its codes are the fixed-point values
+// m 2^-21 (the run-of-zeros codes above; the next code, 0x4000, is 2^-7
+// itself and also m 2^-21): the nearest code, ties away from zero, is |x|
+// 2^21 rounded half up, one v_cvt_rpi_i32_f32 on the device (as in the
+// FP16C encoder's denormal range), with the sign of x.  Equal to the table
+// encoder there (checked on the host for every such float, and on the
+// device as part of the exhaustive encode test).
+constexpr float kP160sFixedBound = 0x1p-7f;
+__host__ __device__ __forceinline__ uint16_t p160s_encode_fixed(float x) {
+    const uint32_t b = f2u(x);
+    const float y = u2f(b & 0x7FFFFFFFu) * 0x1p21f;       // exact: a power of two
+#if defined(__HIP_DEVICE_COMPILE__)
+    int32_t m;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(m) : "v"(y));
+#else
+    const int32_t m = y < 0.5f ? 0 : (int32_t)(y + 0.5f);  // y + 0.5 exact for y in [0.5, 2^14]
+#endif
+    return (uint16_t)(((b >> 16) & 0x8000u) | (uint32_t)m);
+}
+
 // Asymmetric P16_2C: r leading zeros close with a one (no regime sign), then
 // 2 exponent bits and 12 - r mantissa bits; value 2^(-3-4r+e)(1 + m/2^(12-r)).
 // The 15-bit magnitude converted to float does the regime count: its leading
@@ -275,6 +295,15 @@ struct RawCodec {
     template <class A> __device__ __forceinline__ static auto store_raw(A v, const EncEntry* t) {
         return Codec<F>::template store<A>(v, t);
     }
+};
+
+// Formats with an arithmetic encoder for a range of small values (used by
+// wavefronts whose values all lie there; the others take the table).
+template <int F> struct FixedRange { static constexpr bool value = false; };
+template <> struct FixedRange<S_P16_0S> {
+    static constexpr bool value = true;
+    static constexpr float kBound = kP160sFixedBound;   // |x| < kBound
+    __device__ __forceinline__ static uint16_t store(float x) { return p160s_encode_fixed(x); }
 };
 
 // Formats with a cheaper decoder for the codes whose regime is a run of

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "lbm_codecs.h"
@@ -700,8 +701,27 @@ template <int Q, int F, class A>
 __device__ __forceinline__ void out_codes(const LatDev& L, uint32_t fl, const A (&fo)[Q], const EncEntry* tab,
                                           typename Codec<F>::T (&c)[Q]) {
     using T = typename Codec<F>::T;
+    if constexpr (FixedRange<F>::value && std::is_same_v<A, float>) {
+        // the arithmetic encoder where every value of the wavefront is in its
+        // range (wall and EQ lanes are replaced below, whatever they hold);
+        // a NaN fails the comparison and goes to the table
+        bool fixed = (fl & (F_SOLID | F_EQ)) != 0;
+        if (!fixed) {
+            fixed = true;
 #pragma unroll
-    for (int i = 0; i < Q; i++) c[i] = Codec<F>::template store_raw<A>(fo[i], tab);
+            for (int i = 0; i < Q; i++) fixed = fixed && (__builtin_fabsf(fo[i]) < FixedRange<F>::kBound);
+        }
+        if (__all(fixed)) {
+#pragma unroll
+            for (int i = 0; i < Q; i++) c[i] = FixedRange<F>::store(fo[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; i++) c[i] = Codec<F>::template store_raw<A>(fo[i], tab);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) c[i] = Codec<F>::template store_raw<A>(fo[i], tab);
+    }
     if (__any((fl & (F_SOLID | F_EQ)) != 0)) {
         const bool solid = (fl & F_SOLID) != 0, eqc = (fl & F_EQ) != 0;
         T eq[Q];

@@ -176,6 +176,12 @@ __global__ void __launch_bounds__(256) k_encode(int storage, const float* __rest
         case S_FP16: c = Codec<S_FP16>::store<float>(x, nullptr); break;
         case S_FP16S: c = Codec<S_FP16S>::store<float>(x, nullptr); break;
         case S_FP16C: c = Codec<S_FP16C>::store<float>(x, nullptr); break;
+        case S_P16_0S:
+            // as the step encodes: the arithmetic encoder in wavefronts whose
+            // inputs all lie in its range, else the table
+            c = __all(__builtin_fabsf(x) < FixedRange<S_P16_0S>::kBound) ? FixedRange<S_P16_0S>::store(x)
+                                                                           : table_encode(x, s_tab, enc_window_lo(storage));
+            break;
         default: c = table_encode(x, s_tab, enc_window_lo(storage)); break;
         }
         out[i] = c;

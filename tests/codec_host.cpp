@@ -1,7 +1,9 @@
 // Host build of the library's codec header (the same decoders and encoder
 // table the kernels use), for a CPU comparison with the oracle:
 //   codec_host <format index> <decoded.bin> <inputs.bin> <codes.bin>
-// writes the FP32 value of every 16-bit code, then encodes the FP32 inputs.
+// writes the FP32 value of every 16-bit code, then encodes the FP32 inputs;
+// exits non-zero where a shortcut (zeros-run decoder, fixed-range encoder)
+// differs from the general codec on its range.
 // Format indices are the library's storage enum (FP16 2 ... P16_2C 7).
 #include <cstdio>
 #include <cstdlib>
@@ -46,6 +48,17 @@ int main(int argc, char** argv) {
             return 5;
         }
         for (size_t i = 0; i < in.size(); i++) out[i] = lbm::table_encode(in[i], tab.data(), lbm::enc_window_lo(fmt));
+        // P16_0S's arithmetic encoder for |x| < 2^-7 must equal the table
+        // encoder on every such float, both signs
+        if (fmt == lbm::S_P16_0S)
+            for (uint32_t u = 0; u < lbm::f2u(lbm::kP160sFixedBound); u++)
+                for (uint32_t sg : {0u, 0x80000000u}) {
+                    const float v = lbm::u2f(u | sg);
+                    if (lbm::p160s_encode_fixed(v) != lbm::table_encode(v, tab.data(), lbm::enc_window_lo(fmt))) {
+                        std::fprintf(stderr, "fixed-range encoder differs at 0x%08x\n", u | sg);
+                        return 9;
+                    }
+                }
     } else if (fmt == lbm::S_FP16C) {
         for (size_t i = 0; i < in.size(); i++) out[i] = lbm::fp16c_encode(in[i]);
     } else {

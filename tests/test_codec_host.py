@@ -3,8 +3,11 @@ kernels include) against the oracle, without a GPU: the decoders on all
 65,536 codes of FP16C and the three posit formats, and the encoders (FP16C's
 arithmetic one, the posits' sign-and-exponent table) on every code value,
 its float neighbours, the midpoints between neighbouring codes and their
-float neighbours, specials and a million random floats.  The GPU tests
-repeat the encoder comparison on all 2^32 floats."""
+float neighbours, specials and a million random floats.  The driver also
+checks the shortcuts against the general codec on their whole range (the
+posits' zeros-run decoders on every such code, P16_0S's fixed-range encoder
+on every float below 2^-7 in magnitude).  The GPU tests repeat the encoder
+comparison on all 2^32 floats."""
 import os
 import subprocess
 
