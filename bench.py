@@ -42,18 +42,44 @@ def ddf_bytes(storage: str) -> int:
     return BYTES.get(storage, 2)
 
 
+def code_only(text: str) -> str:
+    """C++ source without its comments and blank lines, string and character
+    literals kept as they are (a comment-only edit leaves the code the
+    same)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        ch = text[i]
+        if ch in "\"'":
+            j = i + 1
+            while j < n and text[j] != ch:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            i = text.find("\n", i)
+            i = n if i < 0 else i
+        elif text.startswith("/*", i):
+            i = text.find("*/", i + 2)
+            i = n if i < 0 else i + 2
+        else:
+            out.append(ch)
+            i += 1
+    return "\n".join(line.rstrip() for line in "".join(out).splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources the step kernels and their launchers are built
-    from (every file of csrc/ but the host runtime), so that stored
-    counter readings are used only for the kernel they were taken on."""
+    """Hash of the code (comments left out) the step kernels and their
+    launchers are built from (every file of csrc/ but the host runtime), so
+    that stored counter readings are used only for the kernel they were
+    taken on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2112_08926_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name == "lbm_runtime.hip":
             continue
-        with open(os.path.join(csrc, name), "rb") as fh:
+        with open(os.path.join(csrc, name), encoding="utf-8") as fh:
             h.update(name.encode())
-            h.update(fh.read())
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -394,7 +420,7 @@ def accuracy_vs_fp64(formats, n=64, steps=1000):
 
 def traffic_from_profile(storage):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
+    was taken on the current kernel code, comments aside (else None)."""
     path = os.path.join(ROOT, "profiles", f"ldc512_{storage}_traffic.json")
     if not os.path.exists(path):
         return None

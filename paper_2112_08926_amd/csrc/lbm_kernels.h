@@ -1479,9 +1479,10 @@ __device__ __forceinline__ void diag_exchange(const LatDev& L, uint32_t x, uint3
                 if (fs & F_MOVING) mv = 6.0 * VelSet<Q>::w(i) * (cx * L.wall_u[0] + cy * L.wall_u[1] + cz * L.wall_u[2]);
             }
             const double t = 2.0 * fo + mv;                             // c_opp = -c_i
-            // a component 0 adds nothing: the sums start at +0, and a
-            // non-finite t comes with non-finite moments, whose force diag_cell
-            // clears
+            // a component 0 adds nothing: the sums start at +0, and t is
+            // finite unless the DDF is (then so are the moments, and diag_cell
+            // clears the force) or above 2^1022 in magnitude (FP64 storage
+            // only, far outside any flow)
             if (cx) v[7] -= cx * t;
             if (cy) v[8] -= cy * t;
             if (cz) v[9] -= cz * t;
