@@ -298,7 +298,9 @@ struct RawCodec {
 };
 
 // Formats with an arithmetic encoder for a range of small values (used by
-// wavefronts whose values all lie there; the others take the table).
+// wavefronts whose values all lie there; the others take the table).  Its
+// store() takes the values the step stores, which for these formats are the
+// physical ones (raw units 2^-0).
 template <int F> struct FixedRange { static constexpr bool value = false; };
 template <> struct FixedRange<S_P16_0S> {
     static constexpr bool value = true;
