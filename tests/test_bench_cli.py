@@ -38,3 +38,16 @@ def test_committed_traffic_matches_the_current_kernels(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.traffic_from_profile("fp16s") is None
     assert bench.traffic_from_profile("fp32") is None   # no summary for that format
+
+
+def test_hash_ignores_comments_but_not_code():
+    """The kernel hash reads the code without its comments: a comment-only
+    edit keeps the stored counter readings, any change of code (string and
+    character literals included) drops them."""
+    sys.path.insert(0, ROOT)
+    import bench
+    src = 'int a = 1; // one\n/* two\n   lines */ const char* s = "//x /*y*/"; char c = \'/\';\n\nint b;\n'
+    assert bench.code_only(src) == 'int a = 1;\n const char* s = "//x /*y*/"; char c = \'/\';\nint b;'
+    assert bench.code_only(src.replace("// one", "// changed")) == bench.code_only(src)
+    assert bench.code_only(src.replace("a = 1", "a = 2")) != bench.code_only(src)
+    assert bench.code_only(src.replace('"//x /*y*/"', '"//x /*z*/"')) != bench.code_only(src)
