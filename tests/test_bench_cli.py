@@ -1,5 +1,6 @@
-"""Host behaviour of the benchmark's command line (no GPU needed): more than
-one GPU is refused with a message before anything touches a device."""
+"""Host behaviour of the benchmark (no GPU needed): more than one GPU is
+refused with a message before anything touches a device, and the committed
+counter readings are used only for the kernel code they were taken on."""
 import os
 import subprocess
 import sys
