@@ -322,6 +322,33 @@ __device__ __forceinline__ void pull_codes(const LatDev& L, const typename Codec
         return;
     }
     m = ld_mask(L.wall_mask, n);
+    constexpr uint32_t b = sizeof(T);
+    if ((uint64_t)plane * (2 * b) < (1ull << 32)) {
+        // where two planes fit in 32-bit byte offsets, each load takes one
+        // scalar base, the lower plane of the direction's opposite pair
+        // (directions 2k-1 and 2k are opposite) at the lower of the source
+        // row and this cell's row (n = own + x), plus a per-lane offset
+        // picked by one select: the source cell's or, from a wall, this
+        // cell's in the opposite plane (fewer instructions than two 64-bit
+        // addresses per lane; both offsets stay below two planes)
+        const LBM_GLOBAL char* base0 = (const LBM_GLOBAL char*)src;
+        const uint32_t pb = (uint32_t)plane * b;
+        const uint32_t own = rc.rows[4];
+        const uint32_t xb = x * b, xmb = xm * b, xpb = xp * b;
+        c[0] = ld_off(src + own, x);
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            const int lo = (i & 1) ? i : i - 1;
+            const int cx = VelSet<Q>::c[i][0];
+            const uint32_t ri = src_row<Q>(rc, i);
+            const uint32_t r0 = ri < own ? ri : own;
+            const uint32_t sxb = cx > 0 ? xmb : (cx < 0 ? xpb : xb);
+            const uint32_t normal = ((i & 1) ? 0u : pb) + (ri - r0) * b + sxb;
+            const uint32_t bounce = ((i & 1) ? pb : 0u) + (own - r0) * b + xb;
+            c[i] = *(const LBM_GLOBAL T*)(base0 + ((size_t)lo * plane + r0) * b + (((m >> i) & 1u) ? bounce : normal));
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         const T* p = src + ((size_t)i * plane + src_row<Q>(rc, i));
